@@ -1,0 +1,170 @@
+"""Benchmark: log K_v(x) evaluations per second on one MI355X.
+
+Workload: the 2^24-pair scale workload (v ~ U[0, 50], x ~ 10^U[-3, 3], with 25 %
+drawn from the hard bands |v - x| < 1 and v > 20, x < 0.1; seed 1), inputs
+resident in HBM before timing.  One step = one pass of each path over the whole
+batch:
+
+    f32 fwd        log K, FP32 output (the headline value)
+    f32 fwd+bwd    log K and d/dv, d/dx log K times an upstream gradient
+    f64 fwd        log K, FP64 output
+    f64 fwd+bwd
+
+at 128 bins with the Newton bracket.  Every launch runs on torch's current
+stream, so the torch.cuda events around the timed region bracket exactly the
+kernels.  Prints ONE JSON line (rank 0).
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nbins 128] [--no-cpu]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+import workloads  # noqa: E402
+
+# VALU issue cost per element of the dominant kernel (FP32 forward, 128 bins),
+# in lane-slots (one full-rate VALU instruction on one lane = 1 slot; FP32
+# transcendentals = 2, v_rcp_f64 = 4), from the rocprofv3 instruction counters
+# of this workload (see profiles/).  None until measured.
+SLOTS_PER_ELEM = {("f32", 128): None, ("f64", 128): None}
+
+# MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s
+# (= the 78.6 TFLOP/s FP64 / unpacked-FP32 vector peak with an FMA as 2 FLOP).
+PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+
+def parse():
+    p = argparse.ArgumentParser()
+    p.add_argument("--gpus", type=int, default=1)
+    p.add_argument("--steps", type=int, default=20)
+    p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--nbins", type=int, default=128)
+    p.add_argument("--n", type=int, default=1 << 24)
+    p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
+    p.add_argument("--cpu-seconds", type=float, default=12.0)
+    return p.parse_args()
+
+
+def time_path(fn, steps, warmup):
+    import torch
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(steps):
+        fn()
+    end.record()
+    torch.cuda.synchronize()
+    return start.elapsed_time(end) / steps  # ms per step
+
+
+def cpu_baseline(v, x, gpu_f64, budget_s):
+    """The oracle (as it stands) on a bounded stratified sample, on the host cores."""
+    import oracle
+    threads = oracle.default_threads()
+    rng = np.random.default_rng(77)
+    order = rng.permutation(v.size)
+    done = 0
+    chunk = 4096
+    t0 = time.perf_counter()
+    errs = []
+    while True:
+        idx = order[done:done + chunk]
+        ref = oracle.logk(v[idx], x[idx], nthreads=threads)
+        errs.append(np.abs(gpu_f64[idx] - ref) / np.maximum(1.0, np.abs(ref)))
+        done += idx.size
+        if time.perf_counter() - t0 >= budget_s or done >= v.size:
+            break
+    dt = time.perf_counter() - t0
+    return {
+        "value": done / dt,
+        "unit": "evals/s",
+        "cores": threads,
+        "kind": "oracle",
+        "sample": f"{done} random pairs of the 2^24 scale workload, log K only, long-double adaptive quadrature",
+    }, float(np.concatenate(errs).max()), done
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the elementwise path has no "
+                                   "cross-GPU step: shard the batch, one process per GPU)"}))
+        sys.exit(2)
+    import torch
+
+    import paper_2108_11560_amd as bk
+
+    dev = torch.device("cuda:0")
+    v64, x64, strata = workloads.scale_pairs(args.n, seed=1)
+    go64 = workloads.upstream_grad(args.n, seed=13)
+    V = {"f64": torch.tensor(v64, device=dev), "f32": torch.tensor(v64, dtype=torch.float32, device=dev)}
+    X = {"f64": torch.tensor(x64, device=dev), "f32": torch.tensor(x64, dtype=torch.float32, device=dev)}
+    GO = {"f64": torch.tensor(go64, device=dev), "f32": torch.tensor(go64, dtype=torch.float32, device=dev)}
+    nb = args.nbins
+
+    paths = {}
+    for dt in ("f32", "f64"):
+        fwd = lambda dt=dt: bk.logk(V[dt], X[dt], nbins=nb)  # noqa: E731
+        fb = lambda dt=dt: bk.logk_dv_dx(V[dt], X[dt], grad_out=GO[dt], nbins=nb)  # noqa: E731
+        ms_f = time_path(fwd, args.steps, args.warmup)
+        ms_b = time_path(fb, args.steps, args.warmup)
+        paths[f"{dt}_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3)}
+        paths[f"{dt}_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3)}
+
+    head = paths["f32_fwd"]
+    slots = SLOTS_PER_ELEM.get(("f32", nb))
+    achieved = (slots * args.n / (head["ms"] * 1e-3)) if slots else None
+    roofline = {
+        "bound": "alu",
+        "kernel": f"k_logk<float,{nb},false>",
+        "achieved": achieved / 1e12 if achieved else None,
+        "peak": PEAK_SLOTS / 1e12,
+        "unit": "T VALU lane-slots/s",
+        "frac": (achieved / PEAK_SLOTS) if achieved else None,
+        "traffic": None,
+        "slots_per_elem": slots,
+    }
+
+    line = {
+        "metric": "log K_v(x) evals/s FP64 vs FP32+MLP-range (fwd, fwd+bwd) at rel err 1e-12/1e-5",
+        "value": head["evals_per_s"],
+        "unit": "evals/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "scale-2^24", "n": args.n, "nbins": nb, "range": "newton", "seed": 1,
+                   "path": "f32 fwd"},
+        "paths": paths,
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        gpu64 = bk.logk(V["f64"], X["f64"], nbins=nb).cpu().numpy()
+        base, err, _ = cpu_baseline(v64, x64, gpu64, args.cpu_seconds)
+        line["cpu_baseline"] = base
+        line["f64_max_err_vs_oracle_on_sample"] = err
+    else:
+        line["cpu_baseline"] = None
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,125 @@
+/*
+ * bessel.h -- C ABI of libbessel.so: batched log K_v(x), its derivatives in v
+ * and x, and the integration range, on MI355X (gfx950) HIP kernels.
+ *
+ * Method: Takekawa, "Fast parallel calculation of modified Bessel function of
+ * the second kind and its derivatives" (arXiv 2108.11560).  For v real and
+ * x > 0 (Section 2, Eq. (1)-(2)),
+ *     K_v(x) = int_0^inf cosh(v t) exp(-x cosh t) dt.
+ * Each element: find the peak t_p of g(t) = log cosh(v t) - x cosh t
+ * (Section 2.2), bracket [t0, t1] = {t : g(t) >= g(t_p) + log eps} (Section 2.1,
+ * Eq. (7)-(8); Section 2.3), and sum a fixed number of trapezoid bins in log
+ * space (Section 2.4, Eq. (9)-(11) and Eq. (int)).  Derivatives come from the
+ * companion integrals of Section 4.1, Eq. (13), over the same bins.
+ *
+ * Conventions shared by every entry point:
+ *   - Array pointers are DEVICE pointers, contiguous, owned by the caller; the
+ *     library never frees, reallocates or keeps them past the call.
+ *   - Calls are asynchronous on `hip_stream` (a hipStream_t; NULL means the
+ *     default stream).  No entry point synchronises the host on the hot path.
+ *   - `dtype` selects the element type of every floating array of the call:
+ *     BESSEL_F32 (float) or BESSEL_F64 (double).  The truncation margin log eps
+ *     follows the dtype: eps = 2^-23 (F32) or 2^-52 (F64).
+ *   - Output arrays must not overlap input arrays (BESSEL_ERR_ALIAS).
+ *   - Return value: BESSEL_OK (0), or a negative status; the message of the
+ *     last failure on the calling thread is bessel_last_error().  n == 0 is a
+ *     no-op that returns BESSEL_OK.
+ *   - Per-element domain results are not errors (the paper states only v real,
+ *     x > 0):  NaN v or x, or x < 0 -> NaN;  x == 0 -> log K = +inf;
+ *     x == +inf -> log K = -inf;  |v| == inf with finite x > 0 -> log K = +inf;
+ *     derivatives are NaN in all of these.  v < 0 is evaluated at |v|
+ *     (K_{-v} = K_v) with d/dv negated; v == 0 gives d/dv == 0 exactly.
+ */
+#ifndef BESSEL_H
+#define BESSEL_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* element types */
+#define BESSEL_F32 0
+#define BESSEL_F64 1
+
+/* how [t0, t1] is found */
+#define BESSEL_RANGE_NEWTON 0 /* peak by Newton steps, ends by monotone fixed-point + Newton steps */
+#define BESSEL_RANGE_MLP 1    /* learned bracket with a per-element check and Newton fallback */
+
+/* status codes */
+#define BESSEL_OK 0
+#define BESSEL_ERR_ARG (-1)        /* NULL required pointer, n < 0 */
+#define BESSEL_ERR_DTYPE (-2)      /* dtype not BESSEL_F32 / BESSEL_F64 */
+#define BESSEL_ERR_NBINS (-3)      /* nbins outside [BESSEL_MIN_BINS, BESSEL_MAX_BINS] */
+#define BESSEL_ERR_RANGE_MODE (-4) /* unknown range_mode, or BESSEL_RANGE_MLP with mlp == NULL */
+#define BESSEL_ERR_HIP (-5)        /* a HIP launch or runtime call failed */
+#define BESSEL_ERR_ALIAS (-6)      /* an output overlaps an input */
+#define BESSEL_ERR_UNSUPPORTED (-7) /* combination not provided (e.g. MLP range with F64) */
+
+#define BESSEL_MIN_BINS 2
+#define BESSEL_MAX_BINS 4096
+
+/* Opaque learned-range predictor (see the MLP section below). */
+typedef struct bessel_mlp bessel_mlp;
+
+/*
+ * bessel_logk -- logk[i] = log K_{v[i]}(x[i]) for i < n.
+ *   v, x     [n] inputs (dtype).
+ *   logk     [n] output (dtype).
+ *   nbins    number of trapezoid bins n of Eq. (9) (n + 1 nodes); 64, 128 and
+ *            256 run specialised kernels, other values in range a generic one.
+ *   range_mode, mlp   BESSEL_RANGE_NEWTON (mlp ignored, may be NULL) or
+ *            BESSEL_RANGE_MLP (mlp required; F32 only).
+ * Section 2 (Algorithm 3 and Eq. (int)).
+ */
+int bessel_logk(int dtype, int64_t n, const void* v, const void* x, void* logk, int nbins,
+                int range_mode, const bessel_mlp* mlp, void* hip_stream);
+
+/*
+ * bessel_logk_dv_dx -- derivatives of log K in one pass over the same bins:
+ *   dv[i] = d/dv log K_v(x),  dx[i] = d/dx log K_v(x)   at (v[i], x[i]),
+ * each multiplied by grad_out[i] when grad_out is not NULL (the backward of a
+ * scalar loss through log K).  logk (nullable) also receives log K.
+ * Section 4.1, Eq. (13): d/dv K = int t sinh(v t) e^{-x cosh t} dt and
+ * d/dx K = -int cosh t cosh(v t) e^{-x cosh t} dt, divided by K.
+ */
+int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void* x, const void* grad_out,
+                      void* logk, void* dv, void* dx, int nbins, int range_mode,
+                      const bessel_mlp* mlp, void* hip_stream);
+
+/*
+ * bessel_range -- the bracket of Section 2.1 (Eq. (7)-(8)) for the dtype's eps:
+ *   t0[i], t1[i]    integration limits; [t0, t1] contains every t with
+ *                   g(t) >= g(t_p) + log eps (a superset, never a subset);
+ *   tp[i]           (nullable) peak location t_p (Section 2.2);
+ *   logf_peak[i]    (nullable) g at the returned t_p, the shift of Eq. (int);
+ *   fallback[i]     (nullable, uint8) with BESSEL_RANGE_MLP: 1 where the learned
+ *                   bracket failed its check and the Newton bracket was used.
+ * With BESSEL_RANGE_MLP, tp and logf_peak are those of the bracket actually used.
+ */
+int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1,
+                 void* tp, void* logf_peak, int range_mode, const bessel_mlp* mlp,
+                 uint8_t* fallback, void* hip_stream);
+
+/*
+ * bessel_logk_backward -- the backward step of a scalar loss through log K:
+ *   grad_v[i] = grad_out[i] * dv[i],  grad_x[i] = grad_out[i] * dx[i],
+ * where dv, dx are the derivatives a forward bessel_logk_dv_dx call saved.
+ * grad_v or grad_x may be NULL (that gradient is not needed).  Outputs may not
+ * overlap inputs.  Section 4.1 (the derivatives) with the chain rule.
+ */
+int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void* dv, const void* dx,
+                         void* grad_v, void* grad_x, void* hip_stream);
+
+/* Message of the last failed call on the calling thread ("" if none). */
+const char* bessel_last_error(void);
+
+/* Library build string (compiler, target) for logs. */
+const char* bessel_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* BESSEL_H */

@@ -1,0 +1,347 @@
+// bessel_device.hpp -- gfx950 device code for log K_v(x): arithmetic helpers,
+// the bracket finder and the fixed-bin log-space trapezoid.
+//
+// Method: Takekawa, arXiv 2108.11560.
+//   Section 2, Eq. (1)-(2):   K_v(x) = int_0^inf cosh(v t) exp(-x cosh t) dt
+//   Section 2.1, Eq. (3)-(5): g(t) = log cosh(v t) - x cosh t, g', g''
+//   Section 2.1, Eq. (7)-(8): truncation set {t : g(t) >= g(t_p) + log eps}
+//   Section 2.2-2.3:          peak t_p and the ends t0, t1
+//   Section 2.4, Eq. (9)-(11), Eq. (int): n-bin trapezoid, summed relative to g(t_p)
+//   Section 4.1, Eq. (13):    d/dv and d/dx integrands
+//
+// Precision layout, chosen for gfx950 rates (FP64 FMA at the full vector rate,
+// FP32 exp2/log2/rcp/sqrt at half rate, no FP64 transcendentals in hardware):
+//   - bracket search (t_p, t0, t1): FP32 hardware transcendentals, with one
+//     extra nat of margin that absorbs their rounding; every returned end is on
+//     the outside of its crossing, so the bracket is a superset;
+//   - the peak value G = g(t_p): FP64 (it is added straight to log K);
+//   - per-bin argument g(t_m) - G: FP64 linear recurrences for e^{t_m},
+//     e^{-t_m} and 1 - e^{-2 v t_m}, so no transcendental is spent on them;
+//   - per-bin exponential and sums: FP32 hardware exp2 (F32 path) or a
+//     Cody-Waite + Taylor FP64 exp (F64 path).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace bk {
+
+constexpr double kLog2e = 1.4426950408889634074;
+constexpr double kLn2 = 0.69314718055994530942;
+constexpr float kLog2eF = 1.44269504089f;
+constexpr float kLn2F = 0.693147180560f;
+
+// ---------------------------------------------------------------------------
+// FP32 hardware transcendentals (v_exp_f32, v_log_f32, v_rcp_f32, v_sqrt_f32).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float hexp2(float a) { return __builtin_amdgcn_exp2f(a); }
+__device__ __forceinline__ float hlog2(float a) { return __builtin_amdgcn_logf(a); }
+__device__ __forceinline__ float hrcp(float a) { return __builtin_amdgcn_rcpf(a); }
+__device__ __forceinline__ float hsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
+
+// ---------------------------------------------------------------------------
+// FP64 exponential: Cody-Waite reduction a = k ln2 + r with |r| <= ln2/2 (the
+// product k*ln2 is split into a rounded part and its residual, both applied
+// with fused multiply-adds), then the Taylor series of e^r to degree 12
+// (truncation < 1.7e-16 relative on |r| <= 0.3466), then scaling by 2^k.
+// Inputs below -1100 return 0; the caller never passes NaN or +inf.
+// ---------------------------------------------------------------------------
+constexpr double kLn2Hi = 6.93147180559945286227e-01;  // ln 2 rounded to double
+constexpr double kLn2Lo = 2.31904681384629955842e-17;  // ln 2 - kLn2Hi
+
+__device__ __forceinline__ double exp_f64(double a) {
+  a = fmax(a, -1100.0);
+  const double k = __builtin_rint(a * kLog2e);
+  double r = fma(-k, kLn2Hi, a);
+  r = fma(-k, kLn2Lo, r);
+  double p = 1.0 / 479001600.0;  // 1/12!
+  p = fma(p, r, 1.0 / 39916800.0);
+  p = fma(p, r, 1.0 / 3628800.0);
+  p = fma(p, r, 1.0 / 362880.0);
+  p = fma(p, r, 1.0 / 40320.0);
+  p = fma(p, r, 1.0 / 5040.0);
+  p = fma(p, r, 1.0 / 720.0);
+  p = fma(p, r, 1.0 / 120.0);
+  p = fma(p, r, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  p = fma(p, r, 1.0);
+  return __builtin_amdgcn_ldexp(p, (int)k);
+}
+
+// log cosh z for z >= 0, FP64, written so it cannot overflow:
+// z + log(1 + e^{-2z}) - log 2.
+__device__ __forceinline__ double log_cosh_f64(double z) {
+  return z + log1p(exp(-2.0 * z)) - kLn2;
+}
+
+// g_{v,x}(t) = log cosh(v t) - x cosh t (Eq. 3) in FP64; v >= 0, t >= 0.
+__device__ __forceinline__ double g_f64(double v, double x, double t) {
+  return log_cosh_f64(v * t) - x * cosh(t);
+}
+
+// log cosh z for z >= 0, FP32 hardware form (absolute error ~1e-7 |z|).
+__device__ __forceinline__ float log_cosh_f32(float z) {
+  const float q = hexp2(-2.0f * kLog2eF * z);
+  return z + (hlog2(1.0f + q) - 1.0f) * kLn2F;
+}
+
+// ---------------------------------------------------------------------------
+// Bracket (Sections 2.1-2.3), redesigned for fixed trip counts so a wavefront
+// never waits on a slow lane.  All loops below have compile-time trip counts.
+// ---------------------------------------------------------------------------
+struct Bracket {
+  double G;    // g(t_p), FP64
+  float tp;    // peak location (at or to the right of the true peak)
+  float t0;    // lower end (0, or at/left of the crossing)
+  float t1;    // upper end (at/right of the crossing)
+};
+
+constexpr int kPeakIters = 6;   // Newton steps for t_p
+constexpr int kUpperIters = 2;  // fixed-point steps before the final Newton step for t1
+constexpr int kLowerIters = 3;  // fixed-point steps for t0
+
+// Peak t_p > 0 when v^2 > x (Section 2.1).  g' = v tanh(v t) - x sinh t is
+// concave on t >= 0 (g''' <= 0), zero at 0 and at t_p, and g'(t) <= v - x sinh t
+// < 0 for t > asinh(v/x).  Newton steps started at asinh(v/x), right of the
+// root, on a concave function decreasing through the root stay right of it and
+// decrease monotonically; each step is clamped to [0, t] so FP32 rounding can
+// only stall it, never move it left of the root by more than the rounding.
+__device__ __forceinline__ float peak_f32(float v, float x) {
+  const float r = fminf(v * hrcp(x), 1e18f);
+  float t = kLn2F * hlog2(r + hsqrt(fmaf(r, r, 1.0f)));  // asinh(v/x)
+#pragma unroll
+  for (int k = 0; k < kPeakIters; ++k) {
+    const float q = hexp2(-2.0f * kLog2eF * v * t);  // e^{-2 v t}
+    const float rq = hrcp(1.0f + q);
+    const float th = (1.0f - q) * rq;                  // tanh(v t)
+    const float sech2 = 4.0f * q * rq * rq;            // sech^2(v t)
+    const float e = hexp2(kLog2eF * t);
+    const float ei = hrcp(e);
+    const float gp = v * th - 0.5f * x * (e - ei);     // g'(t)   (Eq. 4)
+    const float gpp = v * v * sech2 - 0.5f * x * (e + ei);  // g''(t)  (Eq. 5), < 0 here
+    const float tn = t - gp * hrcp(gpp);
+    t = fminf(t, fmaxf(tn, 0.0f));
+  }
+  return t;
+}
+
+// Upper end t1: F(t) = g(t) - G + L is concave and decreasing beyond the peak.
+// The map T(t) = acosh((log cosh(v t) - G + L) / x) is increasing, has t1 as
+// its fixed point and contracts there (T'(t1) = v tanh(v t1) / (x sinh t1) < 1
+// because g'(t1) < 0); from t_p, inside the bracket, its iterates increase
+// toward t1.  A final Newton step from such an inside point of a concave F
+// lands at or beyond the root, so the returned t1 is outside.
+__device__ __forceinline__ float upper_f32(float v, float x, float tp, float G, float L) {
+  const float rx = hrcp(x);
+  float t = tp;
+#pragma unroll
+  for (int k = 0; k < kUpperIters; ++k) {
+    const float y = fmaxf((log_cosh_f32(v * t) - G + L) * rx, 1.0f);
+    t = kLn2F * hlog2(y + hsqrt((y - 1.0f) * (y + 1.0f)));  // acosh(y)
+  }
+  const float q = hexp2(-2.0f * kLog2eF * v * t);
+  const float lc = v * t + (hlog2(1.0f + q) - 1.0f) * kLn2F;
+  const float e = hexp2(kLog2eF * t);
+  const float ei = hrcp(e);
+  const float F = lc - 0.5f * x * (e + ei) - G + L;
+  const float Fp = v * (1.0f - q) * hrcp(1.0f + q) - 0.5f * x * (e - ei);
+  const float tn = t - F * hrcp(Fp);
+  // Fp < 0 strictly right of the peak; keep t if rounding made the step useless.
+  return (Fp < 0.0f && tn >= t) ? tn : t;
+}
+
+// Lower end t0 > 0, used only when g(0) - G <= -L (Section 2.3).  The map
+// U(t) = acosh(exp(x cosh t + G - L)) / v is increasing with fixed point t0;
+// from t = 0 (outside, where F <= 0) its iterates increase toward t0 and stay
+// outside, so every iterate is a valid lower end.
+__device__ __forceinline__ float lower_f32(float v, float x, float tp, float G, float L) {
+  const float rv = hrcp(v);
+  float t = 0.0f;
+#pragma unroll
+  for (int k = 0; k < kLowerIters; ++k) {
+    const float e = hexp2(kLog2eF * t);
+    const float ch = 0.5f * (e + hrcp(e));
+    const float y = fmaxf(fmaf(x, ch, G - L), 0.0f);
+    // acosh(e^y) = y + log(1 + sqrt(1 - e^{-2y}))
+    const float s = hsqrt(fmaxf(1.0f - hexp2(-2.0f * kLog2eF * y), 0.0f));
+    t = (y + kLn2F * hlog2(1.0f + s)) * rv;
+  }
+  return fminf(t, tp);
+}
+
+// Full bracket for v >= 0 and finite x > 0.  log_eps_margin = -log eps of the
+// output dtype.  The search margin adds one nat plus a term proportional to
+// the magnitudes that FP32 rounds, so the FP32 search cannot land inside the
+// exact log-eps set.
+__device__ __forceinline__ Bracket find_bracket(double v, double x, float log_eps_margin) {
+  Bracket b;
+  const float vf = (float)v, xf = (float)x;
+  float tp = 0.0f;
+  if (v * v > x) tp = peak_f32(vf, xf);
+  const double G = g_f64(v, x, (double)tp);
+  const float Gf = (float)G;
+  const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + 2.0f * xf * coshf(tp));
+  b.G = G;
+  b.tp = tp;
+  b.t1 = upper_f32(vf, xf, tp, Gf, L);
+  const bool need_t0 = (-x - G + (double)L) <= 0.0;
+  b.t0 = need_t0 ? lower_f32(vf, xf, tp, Gf, L) : 0.0f;
+  return b;
+}
+
+// ---------------------------------------------------------------------------
+// Bins (Section 2.4, Eq. (9)-(11) and Eq. (int)).
+//
+// With q = e^{-2 v t} and r = 1 - q, the integrand and its companions are
+//   f        = cosh(v t) e^{-x cosh t}        = e^{A} (2 - r)
+//   d/dv f   = t sinh(v t) e^{-x cosh t}      = e^{A} r t
+//   -d/dx f  = cosh t cosh(v t) e^{-x cosh t} = e^{A} (2 - r) cosh t
+// with A = v t - x cosh t - log 2, so each bin needs one exponential of the
+// shifted argument A - G.  e^{t}, e^{-t} and r follow t_m = t0 + m h by
+// multiplication:  e^{t+h} = e^t e^h,  r(t+h) = r(t) e^{-2vh} + (1 - e^{-2vh}),
+// the last with positive terms only, so r keeps its relative accuracy as v -> 0.
+// The sums are S0 = sum c_m f_m, Sv = sum c_m d/dv f_m, Sx = sum c_m (-d/dx f_m),
+// with c_0 = c_n = 1/2 (Eq. (11)); then
+//   log K = G + log(h S0),  d/dv log K = Sv / S0,  d/dx log K = -Sx / S0.
+// ---------------------------------------------------------------------------
+struct BinSums {
+  double S0, Sv, Sx;  // Sx carries 2 cosh t (halved by the caller)
+};
+
+// FP64 bins.  Chunks of kChunk nodes; e^{t} and e^{-t} are recomputed with
+// exp_f64 at each chunk start so their product recurrences never run more than
+// kChunk steps (relative error <= ~kChunk ulp).  Nodes m = 0 .. nb; the node
+// weight is 1/2 at m = 0 and m = nb (Eq. (11)).
+constexpr int kChunk = 16;
+
+template <bool GRAD>
+__device__ __forceinline__ void node_f64(double w, double r, double t, double ch2, BinSums& s) {
+  s.S0 = fma(w, 2.0 - r, s.S0);
+  if (GRAD) {
+    s.Sv = fma(w * r, t, s.Sv);
+    s.Sx = fma(w * (2.0 - r), ch2, s.Sx);
+  }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1) {
+  const double h = (t1 - t0) / (double)nb;
+  const double Gs = G + kLn2;
+  const double xh = 0.5 * x;
+  const double eh = exp_f64(h), ehi = exp_f64(-h);
+  const double Q = exp_f64(-2.0 * v * h);
+  const double E2 = -expm1(-2.0 * v * h);
+  double r = -expm1(-2.0 * v * t0);
+  double E = 1.0, Ei = 1.0;
+  BinSums s{0.0, 0.0, 0.0};
+  const int nchunks = nb / kChunk;
+  for (int c = 0; c < nchunks; ++c) {
+    const double ta = fma((double)(c * kChunk), h, t0);
+    E = exp_f64(ta);
+    Ei = exp_f64(-ta);
+#pragma unroll
+    for (int b = 0; b < kChunk; ++b) {
+      const double t = fma((double)b, h, ta);
+      const double ch2 = E + Ei;
+      double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+      if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
+      node_f64<GRAD>(w, r, t, ch2, s);
+      E *= eh;
+      Ei *= ehi;
+      r = fma(r, Q, E2);
+    }
+  }
+  // remainder nodes when nb is not a multiple of kChunk
+  for (int m = nchunks * kChunk; m < nb; ++m) {
+    const double t = fma((double)m, h, t0);
+    E = exp_f64(t);
+    Ei = exp_f64(-t);
+    const double ch2 = E + Ei;
+    double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    if (m == 0) w *= 0.5;
+    node_f64<GRAD>(w, r, t, ch2, s);
+    r = fma(r, Q, E2);
+  }
+  // last node m = nb at t1, weight 1/2, from scratch (E may be stale after a remainder)
+  {
+    const double t = t1;
+    E = exp_f64(t);
+    Ei = exp_f64(-t);
+    const double ch2 = E + Ei;
+    const double w = 0.5 * exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    node_f64<GRAD>(w, r, t, ch2, s);
+  }
+  return s;
+}
+
+// FP32 bins: the argument A - G is formed in FP64 from the recurrences (so no
+// FP32 cancellation between v t, x cosh t and G, which reach ~1e3), already
+// scaled by log2 e; then one hardware exp2 per node and FP32 partial sums per
+// chunk, accumulated in FP64 across chunks.
+template <bool GRAD>
+__device__ __forceinline__ void node_f32(float w, double r, double t, double ch2, float& s0, float& sv, float& sx) {
+  const float rf = (float)r;
+  s0 = fmaf(w, 2.0f - rf, s0);
+  if (GRAD) {
+    sv = fmaf(w * rf, (float)t, sv);
+    sx = fmaf(w * (2.0f - rf), (float)ch2, sx);
+  }
+}
+
+template <bool GRAD>
+__device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G, double t0, double t1) {
+  const double h = (t1 - t0) / (double)nb;
+  const double vl = v * kLog2e;
+  const double xl = 0.5 * x * kLog2e;
+  const double Gl = (G + kLn2) * kLog2e;
+  const double eh = exp(h), ehi = exp(-h);
+  const double Q = exp(-2.0 * v * h);
+  const double E2 = -expm1(-2.0 * v * h);
+  double r = -expm1(-2.0 * v * t0);
+  double E = exp(t0), Ei = exp(-t0);
+  BinSums s{0.0, 0.0, 0.0};
+  const int nchunks = nb / kChunk;
+  for (int c = 0; c < nchunks; ++c) {
+    const double ta = fma((double)(c * kChunk), h, t0);
+    float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
+#pragma unroll
+    for (int b = 0; b < kChunk; ++b) {
+      const double t = fma((double)b, h, ta);
+      const double ch2 = E + Ei;
+      float w = hexp2((float)fma(-xl, ch2, fma(vl, t, -Gl)));
+      if (b == 0) w *= (c == 0) ? 0.5f : 1.0f;
+      node_f32<GRAD>(w, r, t, ch2, s0, sv, sx);
+      E *= eh;
+      Ei *= ehi;
+      r = fma(r, Q, E2);
+    }
+    s.S0 += (double)s0;
+    if (GRAD) {
+      s.Sv += (double)sv;
+      s.Sx += (double)sx;
+    }
+  }
+  {
+    float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
+    for (int m = nchunks * kChunk; m <= nb; ++m) {
+      const double t = (m == nb) ? t1 : fma((double)m, h, t0);
+      const double ch2 = E + Ei;
+      float w = hexp2((float)fma(-xl, ch2, fma(vl, t, -Gl)));
+      if (m == 0 || m == nb) w *= 0.5f;
+      node_f32<GRAD>(w, r, t, ch2, s0, sv, sx);
+      E *= eh;
+      Ei *= ehi;
+      r = fma(r, Q, E2);
+    }
+    s.S0 += (double)s0;
+    if (GRAD) {
+      s.Sv += (double)sv;
+      s.Sx += (double)sx;
+    }
+  }
+  return s;
+}
+
+}  // namespace bk

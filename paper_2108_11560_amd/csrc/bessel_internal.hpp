@@ -1,0 +1,33 @@
+// bessel_internal.hpp -- declarations shared by the library's translation units
+// (not part of the public ABI in include/bessel.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "bessel.h"
+
+namespace bk {
+
+constexpr int kBlock = 256;  // 4 wave64 per workgroup
+
+int set_error(int code, const char* fmt, ...);
+const char* last_error();
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
+int check_launch(const char* what);
+int grid_for(int64_t n, dim3& grid);
+
+// Plain Newton-range paths (bessel_kernels.hip).
+int logk_newton(int dtype, int64_t n, const void* v, const void* x, const void* go, void* lk, void* dv, void* dx,
+                int nbins, bool grad, hipStream_t st);
+int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp, void* gpk,
+                 hipStream_t st);
+
+// Learned-range paths (bessel_mlp.hip), F32 only.
+int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
+             bool grad, const bessel_mlp* mlp, hipStream_t st);
+int range_mlp(int64_t n, const float* v, const float* x, float* t0, float* t1, float* tp, float* gpk,
+              uint8_t* fallback, const bessel_mlp* mlp, hipStream_t st);
+
+}  // namespace bk

@@ -1,0 +1,335 @@
+// bessel_kernels.hip -- gfx950 kernels and the C ABI (include/bessel.h) for
+// batched log K_v(x), its v/x derivatives and the integration range.
+//
+// One (v, x) element per lane, SoA inputs loaded coalesced, all per-element
+// state in registers, a fixed bin count per launch so every lane of a
+// wavefront runs the same instruction stream (Section 2.4: the fixed number of
+// divisions is what makes the time per element uniform).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+
+#include "bessel.h"
+#include "bessel_device.hpp"
+#include "bessel_internal.hpp"
+
+namespace bk {
+
+// -log eps of the output dtype: eps = 2^-52 (FP64), 2^-23 (FP32).
+constexpr float kMarginF64 = 36.0436533891171560f;
+constexpr float kMarginF32 = 15.9423851528787422f;
+
+template <typename T>
+__device__ __forceinline__ float margin_of() {
+  return sizeof(T) == 8 ? kMarginF64 : kMarginF32;
+}
+
+// Domain conventions (see bessel.h).  Returns true when the element is outside
+// v real, 0 < x < inf and has been written.
+template <typename T>
+__device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
+  const double nan_ = __builtin_nan("");
+  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0) {
+    logk = nan_; dv = nan_; dx = nan_;
+    return true;
+  }
+  if (x == 0.0 || __builtin_isinf(v)) {
+    logk = __builtin_inf(); dv = nan_; dx = nan_;
+    return true;
+  }
+  if (__builtin_isinf(x)) {
+    logk = -__builtin_inf(); dv = nan_; dx = nan_;
+    return true;
+  }
+  return false;
+}
+
+template <typename T, bool GRAD>
+__device__ __forceinline__ BinSums run_bins(int nb, double v, double x, const Bracket& b) {
+  if constexpr (sizeof(T) == 8) {
+    return bins_f64<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+  } else {
+    return bins_f32<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+  }
+}
+
+// NB > 0: bin count fixed at compile time; NB == 0: runtime nbins.
+template <typename T, int NB, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* __restrict__ vin,
+                                                 const T* __restrict__ xin, const T* __restrict__ gout,
+                                                 T* __restrict__ logk, T* __restrict__ dv,
+                                                 T* __restrict__ dx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int nb = NB > 0 ? NB : nbins;
+  const double vs = (double)vin[i];
+  const double x = (double)xin[i];
+  double lk, dvv, dxv;
+  if (!domain_special<T>(vs, x, lk, dvv, dxv)) {
+    const double v = fabs(vs);
+    const Bracket b = find_bracket(v, x, margin_of<T>());
+    const BinSums s = run_bins<T, GRAD>(nb, v, x, b);
+    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+    lk = b.G + log(h * s.S0);
+    if (GRAD) {
+      dvv = (v == 0.0) ? 0.0 : copysign(s.Sv / s.S0, vs);
+      dxv = -0.5 * s.Sx / s.S0;
+    }
+  }
+  if (GRAD) {
+    if (gout) {
+      const double go = (double)gout[i];
+      dvv *= go;
+      dxv *= go;
+    }
+    dv[i] = (T)dvv;
+    dx[i] = (T)dxv;
+    if (logk) logk[i] = (T)lk;
+  } else {
+    logk[i] = (T)lk;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_range(int64_t n, const T* __restrict__ vin, const T* __restrict__ xin,
+                                                  T* __restrict__ t0, T* __restrict__ t1, T* __restrict__ tp,
+                                                  T* __restrict__ gpk) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const double v = fabs((double)vin[i]);
+  const double x = (double)xin[i];
+  double a, b_, c;
+  if (domain_special<T>((double)vin[i], x, a, b_, c)) {
+    const T nan_ = (T)__builtin_nan("");
+    t0[i] = nan_; t1[i] = nan_;
+    if (tp) tp[i] = nan_;
+    if (gpk) gpk[i] = nan_;
+    return;
+  }
+  const Bracket b = find_bracket(v, x, margin_of<T>());
+  t0[i] = (T)b.t0;
+  t1[i] = (T)b.t1;
+  if (tp) tp[i] = (T)b.tp;
+  if (gpk) gpk[i] = (T)b.G;
+}
+
+// grad_v = go * dv, grad_x = go * dx (either output may be NULL).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_backward(int64_t n, const T* __restrict__ go, const T* __restrict__ dv,
+                                                     const T* __restrict__ dx, T* __restrict__ gv,
+                                                     T* __restrict__ gx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T g = go[i];
+  if (gv) gv[i] = g * dv[i];
+  if (gx) gx[i] = g * dx[i];
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+static thread_local char g_err[512] = "";
+
+int set_error(int code, const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+  return code;
+}
+
+const char* last_error() { return g_err; }
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  if (!a || !b || abytes == 0 || bbytes == 0) return false;
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+int check_launch(const char* what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+  return BESSEL_OK;
+}
+
+int grid_for(int64_t n, dim3& grid) {
+  const int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 0x7fffffffLL) return set_error(BESSEL_ERR_ARG, "n = %lld exceeds the launch limit", (long long)n);
+  grid = dim3((unsigned)blocks);
+  return BESSEL_OK;
+}
+
+template <typename T, bool GRAD>
+static void launch_logk(dim3 grid, hipStream_t st, int64_t n, int nbins, const T* v, const T* x, const T* go, T* lk,
+                        T* dv, T* dx) {
+  switch (nbins) {
+    case 64: k_logk<T, 64, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+    case 128: k_logk<T, 128, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+    case 256: k_logk<T, 256, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+    default: k_logk<T, 0, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+  }
+}
+
+int logk_newton(int dtype, int64_t n, const void* v, const void* x, const void* go, void* lk, void* dv, void* dx,
+                int nbins, bool grad, hipStream_t st) {
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  if (dtype == BESSEL_F64) {
+    if (grad)
+      launch_logk<double, true>(grid, st, n, nbins, (const double*)v, (const double*)x, (const double*)go,
+                                (double*)lk, (double*)dv, (double*)dx);
+    else
+      launch_logk<double, false>(grid, st, n, nbins, (const double*)v, (const double*)x, nullptr, (double*)lk,
+                                 nullptr, nullptr);
+  } else {
+    if (grad)
+      launch_logk<float, true>(grid, st, n, nbins, (const float*)v, (const float*)x, (const float*)go, (float*)lk,
+                               (float*)dv, (float*)dx);
+    else
+      launch_logk<float, false>(grid, st, n, nbins, (const float*)v, (const float*)x, nullptr, (float*)lk, nullptr,
+                                nullptr);
+  }
+  return check_launch("k_logk");
+}
+
+int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp, void* gpk,
+                 hipStream_t st) {
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  if (dtype == BESSEL_F64)
+    k_range<double><<<grid, kBlock, 0, st>>>(n, (const double*)v, (const double*)x, (double*)t0, (double*)t1,
+                                             (double*)tp, (double*)gpk);
+  else
+    k_range<float><<<grid, kBlock, 0, st>>>(n, (const float*)v, (const float*)x, (float*)t0, (float*)t1, (float*)tp,
+                                            (float*)gpk);
+  return check_launch("k_range");
+}
+
+}  // namespace bk
+
+// ---------------------------------------------------------------------------
+// C ABI
+// ---------------------------------------------------------------------------
+using namespace bk;
+
+static size_t elem_size(int dtype) { return dtype == BESSEL_F64 ? 8 : 4; }
+
+static int common_checks(int dtype, int64_t n, const void* v, const void* x, int range_mode, const bessel_mlp* mlp) {
+  if (dtype != BESSEL_F32 && dtype != BESSEL_F64) return set_error(BESSEL_ERR_DTYPE, "dtype %d is not F32/F64", dtype);
+  if (n < 0) return set_error(BESSEL_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n > 0 && (!v || !x)) return set_error(BESSEL_ERR_ARG, "v and x must be non-NULL");
+  if (range_mode != BESSEL_RANGE_NEWTON && range_mode != BESSEL_RANGE_MLP)
+    return set_error(BESSEL_ERR_RANGE_MODE, "unknown range_mode %d", range_mode);
+  if (range_mode == BESSEL_RANGE_MLP && !mlp) return set_error(BESSEL_ERR_RANGE_MODE, "range_mode MLP needs an mlp");
+  if (range_mode == BESSEL_RANGE_MLP && dtype != BESSEL_F32)
+    return set_error(BESSEL_ERR_UNSUPPORTED, "the learned range is provided for F32 only");
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_logk(int dtype, int64_t n, const void* v, const void* x, void* logk, int nbins, int range_mode,
+                           const bessel_mlp* mlp, void* hip_stream) {
+  int rc = common_checks(dtype, n, v, x, range_mode, mlp);
+  if (rc) return rc;
+  if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
+    return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
+  if (n == 0) return BESSEL_OK;
+  if (!logk) return set_error(BESSEL_ERR_ARG, "logk must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  if (overlaps(logk, nb, v, nb) || overlaps(logk, nb, x, nb))
+    return set_error(BESSEL_ERR_ALIAS, "logk overlaps an input");
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (range_mode == BESSEL_RANGE_MLP) return logk_mlp(n, (const float*)v, (const float*)x, nullptr, (float*)logk,
+                                                      nullptr, nullptr, nbins, false, mlp, st);
+  return logk_newton(dtype, n, v, x, nullptr, logk, nullptr, nullptr, nbins, false, st);
+}
+
+extern "C" int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void* x, const void* grad_out, void* logk,
+                                 void* dv, void* dx, int nbins, int range_mode, const bessel_mlp* mlp,
+                                 void* hip_stream) {
+  int rc = common_checks(dtype, n, v, x, range_mode, mlp);
+  if (rc) return rc;
+  if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
+    return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
+  if (n == 0) return BESSEL_OK;
+  if (!dv || !dx) return set_error(BESSEL_ERR_ARG, "dv and dx must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  const void* ins[3] = {v, x, grad_out};
+  void* outs[3] = {dv, dx, logk};
+  for (int a = 0; a < 3; ++a) {
+    for (int b = 0; b < 3; ++b)
+      if (overlaps(outs[a], nb, ins[b], nb)) return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+    for (int b = a + 1; b < 3; ++b)
+      if (overlaps(outs[a], nb, outs[b], nb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (range_mode == BESSEL_RANGE_MLP)
+    return logk_mlp(n, (const float*)v, (const float*)x, (const float*)grad_out, (float*)logk, (float*)dv, (float*)dx,
+                    nbins, true, mlp, st);
+  return logk_newton(dtype, n, v, x, grad_out, logk, dv, dx, nbins, true, st);
+}
+
+extern "C" int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp,
+                            void* logf_peak, int range_mode, const bessel_mlp* mlp, uint8_t* fallback,
+                            void* hip_stream) {
+  int rc = common_checks(dtype, n, v, x, range_mode, mlp);
+  if (rc) return rc;
+  if (n == 0) return BESSEL_OK;
+  if (!t0 || !t1) return set_error(BESSEL_ERR_ARG, "t0 and t1 must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  const void* ins[2] = {v, x};
+  void* outs[4] = {t0, t1, tp, logf_peak};
+  for (int a = 0; a < 4; ++a) {
+    for (int b = 0; b < 2; ++b)
+      if (overlaps(outs[a], nb, ins[b], nb)) return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+    for (int b = a + 1; b < 4; ++b)
+      if (overlaps(outs[a], nb, outs[b], nb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
+    if (fallback && overlaps(outs[a], nb, fallback, (size_t)n))
+      return set_error(BESSEL_ERR_ALIAS, "fallback overlaps an output");
+  }
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (range_mode == BESSEL_RANGE_MLP)
+    return range_mlp(n, (const float*)v, (const float*)x, (float*)t0, (float*)t1, (float*)tp, (float*)logf_peak,
+                     fallback, mlp, st);
+  return range_newton(dtype, n, v, x, t0, t1, tp, logf_peak, st);
+}
+
+extern "C" int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void* dv, const void* dx,
+                                    void* grad_v, void* grad_x, void* hip_stream) {
+  if (dtype != BESSEL_F32 && dtype != BESSEL_F64) return set_error(BESSEL_ERR_DTYPE, "dtype %d is not F32/F64", dtype);
+  if (n < 0) return set_error(BESSEL_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n == 0) return BESSEL_OK;
+  if (!grad_out || (grad_v && !dv) || (grad_x && !dx))
+    return set_error(BESSEL_ERR_ARG, "grad_out, and dv/dx for each requested gradient, must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  const void* ins[3] = {grad_out, dv, dx};
+  for (int b = 0; b < 3; ++b)
+    if (overlaps(grad_v, nb, ins[b], nb) || overlaps(grad_x, nb, ins[b], nb))
+      return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+  if (overlaps(grad_v, nb, grad_x, nb)) return set_error(BESSEL_ERR_ALIAS, "grad_v overlaps grad_x");
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (dtype == BESSEL_F64)
+    k_backward<double><<<grid, kBlock, 0, st>>>(n, (const double*)grad_out, (const double*)dv, (const double*)dx,
+                                                (double*)grad_v, (double*)grad_x);
+  else
+    k_backward<float><<<grid, kBlock, 0, st>>>(n, (const float*)grad_out, (const float*)dv, (const float*)dx,
+                                               (float*)grad_v, (float*)grad_x);
+  return check_launch("k_backward");
+}
+
+extern "C" const char* bessel_last_error(void) { return last_error(); }
+
+#define BK_STR2(a) #a
+#define BK_STR(a) BK_STR2(a)
+extern "C" const char* bessel_version(void) {
+  return "libbessel gfx950, HIP " BK_STR(HIP_VERSION_MAJOR) "." BK_STR(HIP_VERSION_MINOR) ", " __VERSION__;
+}
