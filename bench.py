@@ -53,6 +53,8 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 24)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--copy-check", action="store_true",
+                   help="also run a plain 256 MiB device copy (calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
 
 
@@ -114,6 +116,14 @@ def main():
     X = {"f64": torch.tensor(x64, device=dev), "f32": torch.tensor(x64, dtype=torch.float32, device=dev)}
     GO = {"f64": torch.tensor(go64, device=dev), "f32": torch.tensor(go64, dtype=torch.float32, device=dev)}
     nb = args.nbins
+
+    if args.copy_check:
+        src = torch.ones(1 << 26, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     paths = {}
     for dt in ("f32", "f64"):

@@ -40,45 +40,117 @@ __device__ __forceinline__ float hrcp(float a) { return __builtin_amdgcn_rcpf(a)
 __device__ __forceinline__ float hsqrt(float a) { return __builtin_amdgcn_sqrtf(a); }
 
 // ---------------------------------------------------------------------------
-// FP64 exponential: Cody-Waite reduction a = k ln2 + r with |r| <= ln2/2 (the
-// product k*ln2 is split into a rounded part and its residual, both applied
-// with fused multiply-adds), then the Taylor series of e^r to degree 12
-// (truncation < 1.7e-16 relative on |r| <= 0.3466), then scaling by 2^k.
-// Inputs below -1100 return 0; the caller never passes NaN or +inf.
+// FP64 elementary functions written for this kernel's argument ranges.
+//
+// exp: a = k ln2 + r with k = nearest integer to a log2(e), obtained by adding
+// 1.5 * 2^52 (the sum's low mantissa bits are k); r = a - k ln2 with ln 2 split
+// into its double rounding and the residual (Cody-Waite), each applied with a
+// fused multiply-add; e^r by a degree-10 polynomial with minimax relative error
+// 3.0e-16 on |r| <= ln2/2 (coefficients from gen_exp_poly.py); 2^k applied by
+// adding k to the exponent field.
 // ---------------------------------------------------------------------------
-constexpr double kLn2Hi = 6.93147180559945286227e-01;  // ln 2 rounded to double
-constexpr double kLn2Lo = 2.31904681384629955842e-17;  // ln 2 - kLn2Hi
+constexpr double kLn2D = 6.93147180559945286227e-01;   // ln 2 rounded to double
+constexpr double kLn2Lo = 2.31904681384629955842e-17;  // ln 2 - kLn2D
+constexpr double kRoundMagic = 6755399441055744.0;     // 1.5 * 2^52
 
-__device__ __forceinline__ double exp_f64(double a) {
-  a = fmax(a, -1100.0);
-  const double k = __builtin_rint(a * kLog2e);
-  double r = fma(-k, kLn2Hi, a);
-  r = fma(-k, kLn2Lo, r);
-  double p = 1.0 / 479001600.0;  // 1/12!
-  p = fma(p, r, 1.0 / 39916800.0);
-  p = fma(p, r, 1.0 / 3628800.0);
-  p = fma(p, r, 1.0 / 362880.0);
-  p = fma(p, r, 1.0 / 40320.0);
-  p = fma(p, r, 1.0 / 5040.0);
-  p = fma(p, r, 1.0 / 720.0);
-  p = fma(p, r, 1.0 / 120.0);
-  p = fma(p, r, 1.0 / 24.0);
-  p = fma(p, r, 1.0 / 6.0);
-  p = fma(p, r, 0.5);
-  p = fma(p, r, 1.0);
-  p = fma(p, r, 1.0);
-  return __builtin_amdgcn_ldexp(p, (int)k);
+struct ExpParts {
+  double em1;  // e^r - 1
+  int k;       // e^a = 2^k (1 + em1)
+};
+
+__device__ __forceinline__ ExpParts exp_parts(double a) {
+  a = fmax(a, -708.0);  // keeps 2^k normal; e^-708 is below every term that matters
+  const double kd = fma(a, kLog2e, kRoundMagic);
+  const double kf = kd - kRoundMagic;
+  const double r = fma(-kf, kLn2Lo, fma(-kf, kLn2D, a));
+  double p = 2.748844352290197e-07;
+  p = fma(p, r, 2.7639768251354328e-06);
+  p = fma(p, r, 2.480191768787707e-05);
+  p = fma(p, r, 0.00019841171384225596);
+  p = fma(p, r, 0.001388888849913829);
+  p = fma(p, r, 0.008333333384665794);
+  p = fma(p, r, 0.041666666668426014);
+  p = fma(p, r, 0.16666666666557742);
+  p = fma(p, r, 0.49999999999997286);
+  p = fma(p, r, 1.0000000000000064);
+  ExpParts e;
+  e.em1 = p * r;
+  e.k = __double2loint(kd);
+  return e;
 }
 
-// log cosh z for z >= 0, FP64, written so it cannot overflow:
-// z + log(1 + e^{-2z}) - log 2.
+// x * 2^k for x in [0.5, 2) and 2^k normal: add k to the exponent field.
+__device__ __forceinline__ double scale2k(double x, int k) {
+  return __hiloint2double((int)((unsigned)__double2hiint(x) + ((unsigned)k << 20)), __double2loint(x));
+}
+
+__device__ __forceinline__ double exp_f64(double a) {
+  const ExpParts e = exp_parts(a);
+  return scale2k(1.0 + e.em1, e.k);
+}
+
+// 1 - e^{-z} for z >= 0 with relative accuracy as z -> 0.
+__device__ __forceinline__ double one_minus_exp_neg(double z) {
+  const ExpParts e = exp_parts(-z);
+  return (e.k == 0) ? -e.em1 : 1.0 - scale2k(1.0 + e.em1, e.k);
+}
+
+// 1/y: hardware estimate refined by two Newton steps.
+__device__ __forceinline__ double rcp_f64(double y) {
+  double r = __builtin_amdgcn_rcp(y);
+  double e = fma(-y, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-y, r, 1.0);
+  return fma(r, e, r);
+}
+
+// log y for finite y > 0 in the normal range: y = 2^e m with m in
+// [sqrt(1/2), sqrt(2)), log m = 2 atanh(s), s = (m - 1)/(m + 1), |s| <= 0.1716,
+// series in s^2 to s^22 (truncation < 1e-17 relative).
+__device__ __forceinline__ double log_f64(double y) {
+  int hi = __double2hiint(y);
+  int e = (hi >> 20) - 1023;
+  hi = (hi & 0x000fffff) | 0x3ff00000;  // m in [1, 2)
+  if (hi > 0x3ff6a09e) {                 // m > sqrt(2): halve
+    hi -= 0x00100000;
+    e += 1;
+  }
+  const double m = __hiloint2double(hi, __double2loint(y));
+  const double num = m - 1.0;
+  const double den = m + 1.0;
+  const double rd = rcp_f64(den);
+  double s = num * rd;
+  s = fma(fma(-den, s, num), rd, s);  // one correction step on the quotient
+  const double s2 = s * s;
+  double p = 1.0 / 23.0;
+  p = fma(p, s2, 1.0 / 21.0);
+  p = fma(p, s2, 1.0 / 19.0);
+  p = fma(p, s2, 1.0 / 17.0);
+  p = fma(p, s2, 1.0 / 15.0);
+  p = fma(p, s2, 1.0 / 13.0);
+  p = fma(p, s2, 1.0 / 11.0);
+  p = fma(p, s2, 1.0 / 9.0);
+  p = fma(p, s2, 1.0 / 7.0);
+  p = fma(p, s2, 1.0 / 5.0);
+  p = fma(p, s2, 1.0 / 3.0);
+  const double lm = fma(2.0 * s * s2, p, 2.0 * s);
+  return fma((double)e, kLn2D, lm);
+}
+
+// cosh t for t >= 0 from e^t and its reciprocal.
+__device__ __forceinline__ double cosh_f64(double t) {
+  const double E = exp_f64(t);
+  return 0.5 * (E + rcp_f64(E));
+}
+
+// log cosh z for z >= 0: z + log(1 + e^{-2z}) - log 2 (absolute error ~1e-16 |z|).
 __device__ __forceinline__ double log_cosh_f64(double z) {
-  return z + log1p(exp(-2.0 * z)) - kLn2;
+  return z + log_f64(1.0 + exp_f64(-2.0 * z)) - kLn2;
 }
 
 // g_{v,x}(t) = log cosh(v t) - x cosh t (Eq. 3) in FP64; v >= 0, t >= 0.
 __device__ __forceinline__ double g_f64(double v, double x, double t) {
-  return log_cosh_f64(v * t) - x * cosh(t);
+  return log_cosh_f64(v * t) - x * cosh_f64(t);
 }
 
 // log cosh z for z >= 0, FP32 hardware form (absolute error ~1e-7 |z|).
@@ -98,7 +170,7 @@ struct Bracket {
   float t1;    // upper end (at/right of the crossing)
 };
 
-constexpr int kPeakIters = 6;   // Newton steps for t_p
+constexpr int kPeakIters = 5;   // Newton steps for t_p
 constexpr int kUpperIters = 2;  // fixed-point steps before the final Newton step for t1
 constexpr int kLowerIters = 3;  // fixed-point steps for t0
 
@@ -182,7 +254,8 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
   if (v * v > x) tp = peak_f32(vf, xf);
   const double G = g_f64(v, x, (double)tp);
   const float Gf = (float)G;
-  const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + 2.0f * xf * coshf(tp));
+  const float etp = hexp2(kLog2eF * tp);
+  const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + xf * (etp + hrcp(etp)));
   b.G = G;
   b.tp = tp;
   b.t1 = upper_f32(vf, xf, tp, Gf, L);
@@ -198,124 +271,130 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
 //   f        = cosh(v t) e^{-x cosh t}        = e^{A} (2 - r)
 //   d/dv f   = t sinh(v t) e^{-x cosh t}      = e^{A} r t
 //   -d/dx f  = cosh t cosh(v t) e^{-x cosh t} = e^{A} (2 - r) cosh t
-// with A = v t - x cosh t - log 2, so each bin needs one exponential of the
-// shifted argument A - G.  e^{t}, e^{-t} and r follow t_m = t0 + m h by
-// multiplication:  e^{t+h} = e^t e^h,  r(t+h) = r(t) e^{-2vh} + (1 - e^{-2vh}),
-// the last with positive terms only, so r keeps its relative accuracy as v -> 0.
+// with A = v t - x cosh t - log 2, so each node needs one exponential of the
+// shifted argument A - G.  Along t_m = t0 + m h every other factor follows by
+// cheap recurrences instead of transcendentals:
+//   e^{t+h} = e^t e^h,  e^{-(t+h)} = e^{-t} e^{-h}       (FP64 path, re-anchored)
+//   cosh(t+h) = 2 cosh(h) cosh(t) - cosh(t-h)            (FP32 path)
+//   r(t+h) = r(t) e^{-2vh} + (1 - e^{-2vh})               (only positive terms,
+//                                                           so r = 1 - q stays
+//                                                           accurate as v -> 0)
 // The sums are S0 = sum c_m f_m, Sv = sum c_m d/dv f_m, Sx = sum c_m (-d/dx f_m),
 // with c_0 = c_n = 1/2 (Eq. (11)); then
 //   log K = G + log(h S0),  d/dv log K = Sv / S0,  d/dx log K = -Sx / S0.
 // ---------------------------------------------------------------------------
 struct BinSums {
-  double S0, Sv, Sx;  // Sx carries 2 cosh t (halved by the caller)
+  double S0, Sv, Sx;
 };
 
-// FP64 bins.  Chunks of kChunk nodes; e^{t} and e^{-t} are recomputed with
-// exp_f64 at each chunk start so their product recurrences never run more than
-// kChunk steps (relative error <= ~kChunk ulp).  Nodes m = 0 .. nb; the node
-// weight is 1/2 at m = 0 and m = nb (Eq. (11)).
-constexpr int kChunk = 16;
+constexpr int kChunk = 16;  // nodes per unrolled chunk
 
+// One node's contribution.  The forward and the derivative kernels accumulate
+// S0 with the same operations, so log K does not depend on whether the
+// derivatives are requested.
 template <bool GRAD>
-__device__ __forceinline__ void node_f64(double w, double r, double t, double ch2, BinSums& s) {
+__device__ __forceinline__ void node_f64(double w, double r, double t, double ch, BinSums& s) {
   s.S0 = fma(w, 2.0 - r, s.S0);
   if (GRAD) {
     s.Sv = fma(w * r, t, s.Sv);
-    s.Sx = fma(w * (2.0 - r), ch2, s.Sx);
+    s.Sx = fma(w * (2.0 - r), ch, s.Sx);
   }
 }
 
+template <bool GRAD>
+__device__ __forceinline__ void node_f32(float w, double r, float t, double ch, float& s0, float& sv, float& sx) {
+  const float rf = (float)r;
+  s0 = fmaf(w, 2.0f - rf, s0);
+  if (GRAD) {
+    sv = fmaf(w * rf, t, sv);
+    sx = fmaf(w * (2.0f - rf), (float)ch, sx);
+  }
+}
+
+// FP64 bins.  e^{t} and e^{-t} are recomputed at each chunk start so their
+// product recurrences never run more than kChunk steps (relative error within
+// ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).
 template <bool GRAD>
 __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1) {
   const double h = (t1 - t0) / (double)nb;
   const double Gs = G + kLn2;
   const double xh = 0.5 * x;
-  const double eh = exp_f64(h), ehi = exp_f64(-h);
+  const double eh = exp_f64(h), ehi = rcp_f64(eh);
   const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = -expm1(-2.0 * v * h);
-  double r = -expm1(-2.0 * v * t0);
-  double E = 1.0, Ei = 1.0;
+  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  double r = one_minus_exp_neg(2.0 * v * t0);
   BinSums s{0.0, 0.0, 0.0};
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
-    E = exp_f64(ta);
-    Ei = exp_f64(-ta);
+    double E = exp_f64(ta);
+    double Ei = rcp_f64(E);
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
       const double t = fma((double)b, h, ta);
       const double ch2 = E + Ei;
       double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
       if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
-      node_f64<GRAD>(w, r, t, ch2, s);
+      node_f64<GRAD>(w, r, t, 0.5 * ch2, s);
+      r = fma(r, Q, E2);
       E *= eh;
       Ei *= ehi;
-      r = fma(r, Q, E2);
     }
   }
-  // remainder nodes when nb is not a multiple of kChunk
-  for (int m = nchunks * kChunk; m < nb; ++m) {
-    const double t = fma((double)m, h, t0);
-    E = exp_f64(t);
-    Ei = exp_f64(-t);
-    const double ch2 = E + Ei;
+  // remainder nodes (nb not a multiple of kChunk) and the last node m = nb
+  for (int m = nchunks * kChunk; m <= nb; ++m) {
+    const double t = (m == nb) ? t1 : fma((double)m, h, t0);
+    const double E = exp_f64(t);
+    const double ch2 = E + rcp_f64(E);
     double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
-    if (m == 0) w *= 0.5;
-    node_f64<GRAD>(w, r, t, ch2, s);
+    if (m == 0 || m == nb) w *= 0.5;
+    node_f64<GRAD>(w, r, t, 0.5 * ch2, s);
     r = fma(r, Q, E2);
-  }
-  // last node m = nb at t1, weight 1/2, from scratch (E may be stale after a remainder)
-  {
-    const double t = t1;
-    E = exp_f64(t);
-    Ei = exp_f64(-t);
-    const double ch2 = E + Ei;
-    const double w = 0.5 * exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
-    node_f64<GRAD>(w, r, t, ch2, s);
   }
   return s;
 }
 
-// FP32 bins: the argument A - G is formed in FP64 from the recurrences (so no
-// FP32 cancellation between v t, x cosh t and G, which reach ~1e3), already
-// scaled by log2 e; then one hardware exp2 per node and FP32 partial sums per
-// chunk, accumulated in FP64 across chunks.
-template <bool GRAD>
-__device__ __forceinline__ void node_f32(float w, double r, double t, double ch2, float& s0, float& sv, float& sx) {
-  const float rf = (float)r;
-  s0 = fmaf(w, 2.0f - rf, s0);
-  if (GRAD) {
-    sv = fmaf(w * rf, (float)t, sv);
-    sx = fmaf(w * (2.0f - rf), (float)ch2, sx);
-  }
-}
-
+// FP32 bins: the argument A - G is formed in FP64 (v t, x cosh t and G reach
+// ~1e3 and nearly cancel, which FP32 could not resolve), pre-scaled by log2 e;
+// then one hardware exp2 per node and FP32 partial sums per chunk, added in
+// FP64 across chunks.  cosh t follows the three-term recurrence (one FMA per
+// node; its relative error grows like m eps / (2 sinh h), far below FP32).
 template <bool GRAD>
 __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G, double t0, double t1) {
   const double h = (t1 - t0) / (double)nb;
   const double vl = v * kLog2e;
-  const double xl = 0.5 * x * kLog2e;
+  const double xl = x * kLog2e;
   const double Gl = (G + kLn2) * kLog2e;
-  const double eh = exp(h), ehi = exp(-h);
-  const double Q = exp(-2.0 * v * h);
-  const double E2 = -expm1(-2.0 * v * h);
-  double r = -expm1(-2.0 * v * t0);
-  double E = exp(t0), Ei = exp(-t0);
+  const double dL = vl * h;
+  const double eh = exp_f64(h);
+  const double ehi = rcp_f64(eh);
+  const double c2 = eh + ehi;  // 2 cosh h
+  const double E0 = exp_f64(t0);
+  const double E0i = rcp_f64(E0);
+  double Cp = 0.5 * (E0 * ehi + E0i * eh);  // cosh(t0 - h)
+  double C = 0.5 * (E0 + E0i);              // cosh(t0)
+  const double Q = exp_f64(-2.0 * v * h);
+  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  double r = one_minus_exp_neg(2.0 * v * t0);
+  const double L0 = fma(vl, t0, -Gl);  // (v t - G - log 2) log2 e
   BinSums s{0.0, 0.0, 0.0};
   const int nchunks = nb / kChunk;
+  const float hf = (float)h;
   for (int c = 0; c < nchunks; ++c) {
-    const double ta = fma((double)(c * kChunk), h, t0);
+    // the linear part runs by addition inside a chunk (error <= kChunk ulp of |L|)
+    double L = fma((double)(c * kChunk), dL, L0);
+    const float taf = (float)fma((double)(c * kChunk), h, t0);
     float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
-      const double t = fma((double)b, h, ta);
-      const double ch2 = E + Ei;
-      float w = hexp2((float)fma(-xl, ch2, fma(vl, t, -Gl)));
+      float w = hexp2((float)fma(-xl, C, L));
       if (b == 0) w *= (c == 0) ? 0.5f : 1.0f;
-      node_f32<GRAD>(w, r, t, ch2, s0, sv, sx);
-      E *= eh;
-      Ei *= ehi;
+      node_f32<GRAD>(w, r, GRAD ? fmaf((float)b, hf, taf) : 0.0f, C, s0, sv, sx);
       r = fma(r, Q, E2);
+      L += dL;
+      const double Cn = fma(c2, C, -Cp);
+      Cp = C;
+      C = Cn;
     }
     s.S0 += (double)s0;
     if (GRAD) {
@@ -326,14 +405,15 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   {
     float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
     for (int m = nchunks * kChunk; m <= nb; ++m) {
-      const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-      const double ch2 = E + Ei;
-      float w = hexp2((float)fma(-xl, ch2, fma(vl, t, -Gl)));
+      const double L = (m == nb) ? fma(vl, t1, -Gl) : fma((double)m, dL, L0);
+      float w = hexp2((float)fma(-xl, C, L));
       if (m == 0 || m == nb) w *= 0.5f;
-      node_f32<GRAD>(w, r, t, ch2, s0, sv, sx);
-      E *= eh;
-      Ei *= ehi;
+      const float tf = GRAD ? ((m == nb) ? (float)t1 : (float)fma((double)m, h, t0)) : 0.0f;
+      node_f32<GRAD>(w, r, tf, C, s0, sv, sx);
       r = fma(r, Q, E2);
+      const double Cn = fma(c2, C, -Cp);
+      Cp = C;
+      C = Cn;
     }
     s.S0 += (double)s0;
     if (GRAD) {

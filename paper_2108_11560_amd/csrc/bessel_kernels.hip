@@ -74,10 +74,11 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
     const Bracket b = find_bracket(v, x, margin_of<T>());
     const BinSums s = run_bins<T, GRAD>(nb, v, x, b);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-    lk = b.G + log(h * s.S0);
+    const double rS0 = rcp_f64(s.S0);
+    lk = b.G + log_f64(h * s.S0);
     if (GRAD) {
-      dvv = (v == 0.0) ? 0.0 : copysign(s.Sv / s.S0, vs);
-      dxv = -0.5 * s.Sx / s.S0;
+      dvv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
+      dxv = -s.Sx * rS0;
     }
   }
   if (GRAD) {

@@ -186,16 +186,20 @@ def test_finite_difference_1024(bk):
     h = 1e-6
     dt = torch.float64
     f = lambda a, b: host(bk.logk(to_dev(a, dt), to_dev(b, dt)))  # noqa: E731
-    lk = np.maximum(1.0, np.abs(f(v, x)))
+    lk = f(v, x)
     _, dv, dx = bk.logk_dv_dx(to_dev(v, dt), to_dev(x, dt))
     dv, dx = host(dv), host(dx)
     # log K is even in v, so f(v - h) = f(|v - h|)
     fd_v = (f(v + h, x) - f(np.abs(v - h), x)) / (2 * h)
     hx = h * x
     fd_x = (f(v, x + hx) - f(v, x - hx)) / (2 * hx)
-    # FD error: truncation O(h^2) plus cancellation ~ a few eps |log K| / step
-    assert np.all(np.abs(dv - fd_v) <= 1e-8 * np.maximum(1.0, np.abs(dv)) + 2e-15 * lk / h)
-    assert np.all(np.abs(dx - fd_x) <= 1e-8 * np.maximum(1.0, np.abs(dx)) + 2e-15 * lk / hx)
+    # The forward carries rounding noise of a few eps times the largest term it
+    # cancels (v t_p, x cosh t_p, |log K|); a difference quotient divides that
+    # noise by the step.  Truncation O(h^2) is far below.
+    tp, _, _, _ = oracle.range_exact(v, x, LOG_EPS[dt])
+    noise = 1e-15 * (1.0 + np.abs(lk) + v * tp + x * np.cosh(tp))
+    assert np.all(np.abs(dv - fd_v) <= 1e-8 * np.maximum(1.0, np.abs(dv)) + noise / h)
+    assert np.all(np.abs(dx - fd_x) <= 1e-8 * np.maximum(1.0, np.abs(dx)) + noise / hx)
 
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
@@ -250,9 +254,10 @@ def test_paper_accuracy_grid(bk):
     got = host(bk.logk(to_dev(v, torch.float64), to_dev(x, torch.float64)))
     e = mixed(got, ref)
     assert e.max() <= 1e-12
-    # the paper's metric log10(|Delta| / eps + 1) on log K, for the record
-    metric = np.log10(np.abs(got - ref) / np.finfo(np.float64).eps + 1)
-    assert np.median(metric) <= 1.5
+    # the paper's metric log10(|Delta| / eps + 1), with Delta the mixed error of
+    # log K (|log K| reaches ~400 on this grid, where one output ulp is ~26 eps)
+    metric = np.log10(e / np.finfo(np.float64).eps + 1)
+    assert np.median(metric) <= 1.0 and metric.max() <= 3.0  # at most 1000 eps (the bar, 1e-12, is ~4500 eps)
     ref32 = oracle.logk(v.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64))
     got32 = host(bk.logk(to_dev(v, torch.float32), to_dev(x, torch.float32)))
     assert mixed(got32, ref32).max() <= 1e-5
