@@ -33,15 +33,37 @@ if ROOT not in sys.path:
 
 import workloads  # noqa: E402
 
-# VALU issue cost per element of the dominant kernel (FP32 forward, 128 bins),
-# in lane-slots (one full-rate VALU instruction on one lane = 1 slot; FP32
-# transcendentals = 2, v_rcp_f64 = 4), from the rocprofv3 instruction counters
-# of this workload (see profiles/).  None until measured.
-SLOTS_PER_ELEM = {("f32", 128): None, ("f64", 128): None}
+# Algorithmic VALU work per element, in lane-slots (one full-rate VALU
+# instruction on one lane = 1 slot; an FP32 transcendental = 2, measured half
+# rate; v_rcp_f64 = 4):  W(n) = (n + 1) * W_NODE + W_PRE, from the operation
+# count of the formulation (one table per path in DESIGN.md, "Roofline").
+W_NODE = {("f32", False): 10.0, ("f32", True): 16.0, ("f64", False): 26.5, ("f64", True): 30.5}
+W_PRE = 500.0
 
 # MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s
 # (= the 78.6 TFLOP/s FP64 / unpacked-FP32 vector peak with an FMA as 2 FLOP).
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
+
+# HBM bytes per element of the f32 forward kernel from rocprofv3 FETCH_SIZE
+# (x2: a plain 256 MiB device copy reads back half its size on this counter)
+# plus WRITE_SIZE, taken on the kernel sources whose hash is recorded here.
+TRAFFIC = {"sources_sha256": "ed518000274c4105035593d97cf097408be3e2f5b7564e468f5e738e6f791cbd",
+           "bytes_per_elem": 12.007}  # (65593 * 2 + 65536) KiB per 2^24 elements
+
+
+def kernel_sources_sha256() -> str:
+    import hashlib
+    csrc = os.path.join(ROOT, "paper_2108_11560_amd", "csrc")
+    h = hashlib.sha256()
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".hpp")):
+            with open(os.path.join(csrc, name), "rb") as f:
+                h.update(name.encode() + b"\0" + f.read())
+    return h.hexdigest()
+
+
+def alg_slots(dt: str, grad: bool, nbins: int) -> float:
+    return (nbins + 1) * W_NODE[(dt, grad)] + W_PRE
 
 
 def parse():
@@ -134,18 +156,25 @@ def main():
         paths[f"{dt}_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3)}
         paths[f"{dt}_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3)}
 
+    for key, p in paths.items():
+        dt, grad = key[:3], key.endswith("bwd")
+        p["alg_slots_per_elem"] = alg_slots(dt, grad, nb)
+        p["valu_frac"] = p["alg_slots_per_elem"] * p["evals_per_s"] / PEAK_SLOTS
+
     head = paths["f32_fwd"]
-    slots = SLOTS_PER_ELEM.get(("f32", nb))
-    achieved = (slots * args.n / (head["ms"] * 1e-3)) if slots else None
+    achieved = head["alg_slots_per_elem"] * head["evals_per_s"]
+    traffic = None
+    if TRAFFIC["bytes_per_elem"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        traffic = TRAFFIC["bytes_per_elem"] * args.n
     roofline = {
         "bound": "alu",
         "kernel": f"k_logk<float,{nb},false>",
-        "achieved": achieved / 1e12 if achieved else None,
+        "achieved": achieved / 1e12,
         "peak": PEAK_SLOTS / 1e12,
         "unit": "T VALU lane-slots/s",
-        "frac": (achieved / PEAK_SLOTS) if achieved else None,
-        "traffic": None,
-        "slots_per_elem": slots,
+        "frac": achieved / PEAK_SLOTS,
+        "traffic": traffic,
+        "alg_slots_per_elem": head["alg_slots_per_elem"],
     }
 
     line = {
