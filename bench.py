@@ -75,6 +75,7 @@ def parse():
     p.add_argument("--n", type=int, default=1 << 24)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
     p.add_argument("--cpu-seconds", type=float, default=12.0)
+    p.add_argument("--mlp-steps", type=int, default=20000)
     p.add_argument("--copy-check", action="store_true",
                    help="also run a plain 256 MiB device copy (calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     return p.parse_args()
@@ -94,8 +95,11 @@ def time_path(fn, steps, warmup):
     return start.elapsed_time(end) / steps  # ms per step
 
 
-def cpu_baseline(v, x, gpu_f64, budget_s):
-    """The oracle (as it stands) on a bounded stratified sample, on the host cores."""
+def cpu_baseline(v, x, v32, x32, gpu, budget_s):
+    """The oracle (as it stands) on a bounded random sample, on the host cores.
+
+    The same sample also gives each GPU path's largest mixed error (FP32 paths
+    against the oracle at their FP32-rounded inputs)."""
     import oracle
     threads = oracle.default_threads()
     rng = np.random.default_rng(77)
@@ -103,22 +107,26 @@ def cpu_baseline(v, x, gpu_f64, budget_s):
     done = 0
     chunk = 4096
     t0 = time.perf_counter()
-    errs = []
+    errs = {k: 0.0 for k in gpu}
     while True:
         idx = order[done:done + chunk]
-        ref = oracle.logk(v[idx], x[idx], nthreads=threads)
-        errs.append(np.abs(gpu_f64[idx] - ref) / np.maximum(1.0, np.abs(ref)))
+        ref64 = oracle.logk(v[idx], x[idx], nthreads=threads)
         done += idx.size
-        if time.perf_counter() - t0 >= budget_s or done >= v.size:
+        elapsed = time.perf_counter() - t0
+        ref32 = oracle.logk(v32[idx], x32[idx], nthreads=threads)
+        for k, g in gpu.items():
+            ref = ref64 if k == "f64" else ref32
+            e = np.abs(g[idx] - ref) / np.maximum(1.0, np.abs(ref))
+            errs[k] = max(errs[k], float(e.max()))
+        if elapsed >= budget_s or done >= v.size:
             break
-    dt = time.perf_counter() - t0
     return {
-        "value": done / dt,
+        "value": done / elapsed,
         "unit": "evals/s",
         "cores": threads,
         "kind": "oracle",
         "sample": f"{done} random pairs of the 2^24 scale workload, log K only, long-double adaptive quadrature",
-    }, float(np.concatenate(errs).max()), done
+    }, errs, done
 
 
 def main():
@@ -147,6 +155,22 @@ def main():
         torch.cuda.synchronize()
         del src, dst
 
+    # learned range: train on the 2^20-sample training workload (labels = Newton
+    # brackets), calibrate the two margins on a held-out set; not timed
+    from paper_2108_11560_amd import mlp as M
+    t_train = time.perf_counter()
+    vtr, xtr, _ = workloads.scale_pairs(1 << 20, seed=4)
+    mlp = M.RangeMLP(M.glorot_params(0))
+    losses = mlp.train(torch.tensor(vtr, dtype=torch.float32, device=dev),
+                       torch.tensor(xtr, dtype=torch.float32, device=dev),
+                       steps=args.mlp_steps, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
+    vca, xca, _ = workloads.scale_pairs(1 << 16, seed=8)
+    m1, m0, cal_rate = M.calibrate_margins(mlp, torch.tensor(vca, dtype=torch.float32, device=dev),
+                                           torch.tensor(xca, dtype=torch.float32, device=dev),
+                                           target_fallback=0.005)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t_train
+
     paths = {}
     for dt in ("f32", "f64"):
         fwd = lambda dt=dt: bk.logk(V[dt], X[dt], nbins=nb)  # noqa: E731
@@ -156,7 +180,20 @@ def main():
         paths[f"{dt}_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3)}
         paths[f"{dt}_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3)}
 
+    fwd = lambda: bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
+    fb = lambda: bk.logk_dv_dx(V["f32"], X["f32"], grad_out=GO["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
+    ms_f = time_path(fwd, args.steps, args.warmup)
+    fb_fwd = mlp.fallback_count()
+    ms_b = time_path(fb, args.steps, args.warmup)
+    fb_bwd = mlp.fallback_count()
+    paths["f32_mlp_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3), "fallback_rate": fb_fwd / args.n}
+    paths["f32_mlp_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3), "fallback_rate": fb_bwd / args.n}
+    mlp_info = {"train_steps": args.mlp_steps, "train_seconds": t_train, "final_loss": float(losses[-1]),
+                "margin_t1": m1, "margin_t0": m0, "calibration_fallback_rate": cal_rate}
+
     for key, p in paths.items():
+        if "mlp" in key:
+            continue
         dt, grad = key[:3], key.endswith("bwd")
         p["alg_slots_per_elem"] = alg_slots(dt, grad, nb)
         p["valu_frac"] = p["alg_slots_per_elem"] * p["evals_per_s"] / PEAK_SLOTS
@@ -193,13 +230,19 @@ def main():
         "config": {"workload": "scale-2^24", "n": args.n, "nbins": nb, "range": "newton", "seed": 1,
                    "path": "f32 fwd"},
         "paths": paths,
+        "learned_range": mlp_info,
         "roofline": roofline,
     }
     if not args.no_cpu:
-        gpu64 = bk.logk(V["f64"], X["f64"], nbins=nb).cpu().numpy()
-        base, err, _ = cpu_baseline(v64, x64, gpu64, args.cpu_seconds)
+        gpu = {
+            "f64": bk.logk(V["f64"], X["f64"], nbins=nb).cpu().numpy(),
+            "f32": bk.logk(V["f32"], X["f32"], nbins=nb).double().cpu().numpy(),
+            "f32_mlp": bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp", mlp=mlp).double().cpu().numpy(),
+        }
+        base, errs, _ = cpu_baseline(v64, x64, V["f32"].double().cpu().numpy(), X["f32"].double().cpu().numpy(),
+                                     gpu, args.cpu_seconds)
         line["cpu_baseline"] = base
-        line["f64_max_err_vs_oracle_on_sample"] = err
+        line["max_err_vs_oracle_on_sample"] = errs
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)

@@ -112,6 +112,78 @@ int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, v
 int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void* dv, const void* dx,
                          void* grad_v, void* grad_x, void* hip_stream);
 
+/*
+ * Learned bracket predictor (FP32 path).
+ *
+ * A network 2 -> 64 -> 64 -> 2 (tanh) maps the features of an element,
+ * ((log max(|v|, 1e-3) - m_v)/s_v, (log x - m_x)/s_x), to (y0, y1); the bracket
+ * is t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1).  It is trained
+ * on the method's own Newton brackets (Sections 2.2-2.3 at the FP32 eps), and
+ * at inference (bf16 MFMA for the 64 x 64 layer) every predicted bracket is
+ * checked after the bins: the end terms must lie below eps relative to the
+ * shift and the even-node and odd-node sums must agree to 1e-5.  Elements
+ * that fail are recomputed by the Newton path in a second kernel on the same
+ * stream.
+ *
+ * Parameter vector (host floats, BESSEL_MLP_NPARAMS): W1 (64 x 2, row-major),
+ * b1[64], W2 (64 x 64; W2[i][j] multiplies hidden j of layer 1), b2[64],
+ * W3 (2 x 64), b3[2] (BESSEL_MLP_NWEIGHTS trainable values), then
+ * m_v, s_v, m_x, s_x, margin_t1, margin_t0, 0, 0.
+ *
+ * The handle owns all device memory it uses: parameters, optimizer state, and
+ * workspaces that grow (stream-ordered, on the call's stream) to the largest
+ * n seen.  Calls that use one handle must not overlap in time (serialise them
+ * on one stream); different handles are independent.
+ */
+#define BESSEL_MLP_HIDDEN 64
+#define BESSEL_MLP_NWEIGHTS 4482
+#define BESSEL_MLP_NPARAMS 4490
+
+typedef struct {
+  int64_t steps;      /* Adam steps */
+  int64_t batch;      /* samples per step, drawn with replacement from the n inputs */
+  float lr;           /* learning rate at the first step */
+  float lr_final;     /* learning rate at the last step (exponential decay in between) */
+  float beta1, beta2, adam_eps;
+  float alpha;        /* loss weight on the unsafe side (t0 too large, t1 too small) */
+  uint64_t seed;      /* minibatch draws: splitmix64 of (seed, step, sample) */
+} bessel_mlp_train_cfg;
+
+/* Create a predictor; params (host, nullable: zeros with unit scales) of length nparams. */
+int bessel_mlp_create(const float* params, int64_t nparams, bessel_mlp** out);
+/* Destroy (synchronises the device first).  NULL is a no-op. */
+int bessel_mlp_destroy(bessel_mlp* mlp);
+/* Replace the parameters (host floats) and reset the optimizer state. */
+int bessel_mlp_set_params(bessel_mlp* mlp, const float* params, int64_t nparams);
+/* Copy the parameters to host floats (synchronises the device). */
+int bessel_mlp_get_params(const bessel_mlp* mlp, float* params, int64_t nparams);
+/*
+ * Train on n FP32 device inputs (v, x): labels are the Newton brackets of the
+ * inputs at the FP32 eps, then cfg->steps Adam steps on minibatches.  loss_host
+ * (nullable, cfg->steps floats) receives the loss of each step; when it is
+ * given the call synchronises the stream at the end.
+ */
+int bessel_mlp_train(bessel_mlp* mlp, const bessel_mlp_train_cfg* cfg, int64_t n, const float* v, const float* x,
+                     float* loss_host, void* hip_stream);
+/*
+ * Loss and gradient (BESSEL_MLP_NWEIGHTS floats, same order as the weights) of
+ * the full batch of n device samples with given bracket targets t0, t1 (device),
+ * asymmetry alpha.  loss[1] and grad are device outputs.
+ */
+int bessel_mlp_loss_grad(bessel_mlp* mlp, int64_t n, const float* v, const float* x, const float* t0,
+                         const float* t1, float alpha, float* loss, float* grad, void* hip_stream);
+/* One Adam step (Kingma & Ba, bias-corrected; the handle counts steps from 1)
+ * with a given device gradient of BESSEL_MLP_NWEIGHTS floats. */
+int bessel_mlp_adam_step(bessel_mlp* mlp, const float* grad, float lr, float beta1, float beta2, float eps,
+                         void* hip_stream);
+/* Raw network outputs y[2 i], y[2 i + 1] for n device inputs; mode 0: FP32 with
+ * exact tanh, one element per lane; mode 1: the bf16-MFMA inference of the fused kernel. */
+int bessel_mlp_forward(const bessel_mlp* mlp, int64_t n, const float* v, const float* x, float* y, int mode,
+                       void* hip_stream);
+/* Number of elements of the handle's last learned-range call that fell back to
+ * the Newton bracket (synchronises the device). */
+int bessel_mlp_fallback_count(const bessel_mlp* mlp, int* count);
+
 /* Message of the last failed call on the calling thread ("" if none). */
 const char* bessel_last_error(void);
 

@@ -37,6 +37,15 @@ SIGNATURES = {
     "bessel_logk_dv_dx": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp]),
     "bessel_range": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "bessel_logk_backward": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bessel_mlp_create": (_int, [_vp, _i64, _vp]),
+    "bessel_mlp_destroy": (_int, [_vp]),
+    "bessel_mlp_set_params": (_int, [_vp, _vp, _i64]),
+    "bessel_mlp_get_params": (_int, [_vp, _vp, _i64]),
+    "bessel_mlp_train": (_int, [_vp, _vp, _i64, _vp, _vp, _vp, _vp]),
+    "bessel_mlp_loss_grad": (_int, [_vp, _i64, _vp, _vp, _vp, _vp, ctypes.c_float, _vp, _vp, _vp]),
+    "bessel_mlp_forward": (_int, [_vp, _i64, _vp, _vp, _vp, _int, _vp]),
+    "bessel_mlp_adam_step": (_int, [_vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
+    "bessel_mlp_fallback_count": (_int, [_vp, _vp]),
     "bessel_last_error": (ctypes.c_char_p, []),
     "bessel_version": (ctypes.c_char_p, []),
 }

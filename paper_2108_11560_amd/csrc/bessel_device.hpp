@@ -159,6 +159,25 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
   return z + (hlog2(1.0f + q) - 1.0f) * kLn2F;
 }
 
+// Domain conventions (see include/bessel.h).  Returns true when the element is
+// outside v real, 0 < x < inf; then logk, dv, dx hold the convention's values.
+__device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
+  const double nan_ = __builtin_nan("");
+  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0) {
+    logk = nan_; dv = nan_; dx = nan_;
+    return true;
+  }
+  if (x == 0.0 || __builtin_isinf(v)) {
+    logk = __builtin_inf(); dv = nan_; dx = nan_;
+    return true;
+  }
+  if (__builtin_isinf(x)) {
+    logk = -__builtin_inf(); dv = nan_; dx = nan_;
+    return true;
+  }
+  return false;
+}
+
 // ---------------------------------------------------------------------------
 // Bracket (Sections 2.1-2.3), redesigned for fixed trip counts so a wavefront
 // never waits on a slow lane.  All loops below have compile-time trip counts.
@@ -285,6 +304,12 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
 // ---------------------------------------------------------------------------
 struct BinSums {
   double S0, Sv, Sx;
+  // Filled only by the checked FP32 variant (learned brackets): the sums over
+  // even and over odd nodes (each a trapezoid / midpoint rule of step 2h; their
+  // difference measures the quadrature error), and the unweighted terms at the
+  // two ends, relative to e^{G}.
+  double Seven, Sodd;
+  float term0, termN;
 };
 
 constexpr int kChunk = 16;  // nodes per unrolled chunk
@@ -323,7 +348,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const double Q = exp_f64(-2.0 * v * h);
   const double E2 = one_minus_exp_neg(2.0 * v * h);
   double r = one_minus_exp_neg(2.0 * v * t0);
-  BinSums s{0.0, 0.0, 0.0};
+  BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
@@ -359,7 +384,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
 // then one hardware exp2 per node and FP32 partial sums per chunk, added in
 // FP64 across chunks.  cosh t follows the three-term recurrence (one FMA per
 // node; its relative error grows like m eps / (2 sinh h), far below FP32).
-template <bool GRAD>
+template <bool GRAD, bool CHECK = false>
 __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G, double t0, double t1) {
   const double h = (t1 - t0) / (double)nb;
   const double vl = v * kLog2e;
@@ -377,45 +402,61 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   const double E2 = one_minus_exp_neg(2.0 * v * h);
   double r = one_minus_exp_neg(2.0 * v * t0);
   const double L0 = fma(vl, t0, -Gl);  // (v t - G - log 2) log2 e
-  BinSums s{0.0, 0.0, 0.0};
+  BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
   const int nchunks = nb / kChunk;
   const float hf = (float)h;
   for (int c = 0; c < nchunks; ++c) {
     // the linear part runs by addition inside a chunk (error <= kChunk ulp of |L|)
     double L = fma((double)(c * kChunk), dL, L0);
     const float taf = (float)fma((double)(c * kChunk), h, t0);
-    float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
+    float s0 = 0.0f, sv = 0.0f, sx = 0.0f, s0o = 0.0f;
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
       float w = hexp2((float)fma(-xl, C, L));
+      if (CHECK && b == 0 && c == 0) s.term0 = w * (2.0f - (float)r);
       if (b == 0) w *= (c == 0) ? 0.5f : 1.0f;
-      node_f32<GRAD>(w, r, GRAD ? fmaf((float)b, hf, taf) : 0.0f, C, s0, sv, sx);
+      // the checked variant keeps odd nodes (chunk starts are even) apart
+      node_f32<GRAD>(w, r, GRAD ? fmaf((float)b, hf, taf) : 0.0f, C, (CHECK && (b & 1)) ? s0o : s0, sv, sx);
       r = fma(r, Q, E2);
       L += dL;
       const double Cn = fma(c2, C, -Cp);
       Cp = C;
       C = Cn;
     }
-    s.S0 += (double)s0;
+    if (CHECK) {
+      s.Seven += (double)s0;
+      s.Sodd += (double)s0o;
+      s.S0 += (double)s0 + (double)s0o;
+    } else {
+      s.S0 += (double)s0;
+    }
     if (GRAD) {
       s.Sv += (double)sv;
       s.Sx += (double)sx;
     }
   }
   {
-    float s0 = 0.0f, sv = 0.0f, sx = 0.0f;
+    float s0 = 0.0f, sv = 0.0f, sx = 0.0f, s0o = 0.0f;
     for (int m = nchunks * kChunk; m <= nb; ++m) {
       const double L = (m == nb) ? fma(vl, t1, -Gl) : fma((double)m, dL, L0);
       float w = hexp2((float)fma(-xl, C, L));
+      if (CHECK && m == 0) s.term0 = w * (2.0f - (float)r);
+      if (CHECK && m == nb) s.termN = w * (2.0f - (float)r);
       if (m == 0 || m == nb) w *= 0.5f;
       const float tf = GRAD ? ((m == nb) ? (float)t1 : (float)fma((double)m, h, t0)) : 0.0f;
-      node_f32<GRAD>(w, r, tf, C, s0, sv, sx);
+      node_f32<GRAD>(w, r, tf, C, (CHECK && (m & 1)) ? s0o : s0, sv, sx);
       r = fma(r, Q, E2);
       const double Cn = fma(c2, C, -Cp);
       Cp = C;
       C = Cn;
     }
-    s.S0 += (double)s0;
+    if (CHECK) {
+      s.Seven += (double)s0;
+      s.Sodd += (double)s0o;
+      s.S0 += (double)s0 + (double)s0o;
+    } else {
+      s.S0 += (double)s0;
+    }
     if (GRAD) {
       s.Sv += (double)sv;
       s.Sx += (double)sx;

@@ -28,26 +28,6 @@ __device__ __forceinline__ float margin_of() {
   return sizeof(T) == 8 ? kMarginF64 : kMarginF32;
 }
 
-// Domain conventions (see bessel.h).  Returns true when the element is outside
-// v real, 0 < x < inf and has been written.
-template <typename T>
-__device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
-  const double nan_ = __builtin_nan("");
-  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0) {
-    logk = nan_; dv = nan_; dx = nan_;
-    return true;
-  }
-  if (x == 0.0 || __builtin_isinf(v)) {
-    logk = __builtin_inf(); dv = nan_; dx = nan_;
-    return true;
-  }
-  if (__builtin_isinf(x)) {
-    logk = -__builtin_inf(); dv = nan_; dx = nan_;
-    return true;
-  }
-  return false;
-}
-
 template <typename T, bool GRAD>
 __device__ __forceinline__ BinSums run_bins(int nb, double v, double x, const Bracket& b) {
   if constexpr (sizeof(T) == 8) {
@@ -69,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
   const double vs = (double)vin[i];
   const double x = (double)xin[i];
   double lk, dvv, dxv;
-  if (!domain_special<T>(vs, x, lk, dvv, dxv)) {
+  if (!domain_special(vs, x, lk, dvv, dxv)) {
     const double v = fabs(vs);
     const Bracket b = find_bracket(v, x, margin_of<T>());
     const BinSums s = run_bins<T, GRAD>(nb, v, x, b);
@@ -104,7 +84,7 @@ __global__ __launch_bounds__(kBlock) void k_range(int64_t n, const T* __restrict
   const double v = fabs((double)vin[i]);
   const double x = (double)xin[i];
   double a, b_, c;
-  if (domain_special<T>((double)vin[i], x, a, b_, c)) {
+  if (domain_special((double)vin[i], x, a, b_, c)) {
     const T nan_ = (T)__builtin_nan("");
     t0[i] = nan_; t1[i] = nan_;
     if (tp) tp[i] = nan_;

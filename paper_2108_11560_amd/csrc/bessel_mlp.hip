@@ -1,19 +1,799 @@
-// bessel_mlp.hip -- learned bracket predictor (placeholder until the MLP kernels land).
+// bessel_mlp.hip -- learned bracket predictor for the FP32 path.
+//
+// A small network maps the features of an element to its integration bracket
+// [t0, t1] (the range of Section 2.1, Eq. (7)-(8)), so the peak and bracket
+// searches of Sections 2.2-2.3 are skipped.  It is trained on brackets produced
+// by the method's own range finder (find_bracket at the FP32 margin).  Every
+// predicted bracket is checked after the bins; elements that fail are
+// compacted into a worklist and recomputed by the Newton path, which therefore
+// remains both the fallback and the judge of the predictor.
+//
+//   features  z = ((log max(|v|, 1e-3) - m_v) / s_v, (log x - m_x) / s_x)
+//   network   h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3
+//             (2 -> 64 -> 64 -> 2; FP32 master weights)
+//   bracket   t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1)
+//   targets   y0* = t0/t1, y1* = log t1 of the Newton bracket
+//   loss      mean of 1/2 (w0 e0^2 + w1 e1^2), e = y - y*, with weight alpha on
+//             the unsafe side (t0 too large, t1 too small)
+//
+// Parameter vector (floats): W1 (64 x 2, row-major), b1[64], W2 (64 x 64,
+// W2[i][j] multiplies h1[j]), b2[64], W3 (2 x 64), b3[2]  -- 4482 trainable
+// values -- then m_v, s_v, m_x, s_x, margin_t1, margin_t0, 0, 0.
 #include <hip/hip_runtime.h>
 
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <new>
+
 #include "bessel.h"
+#include "bessel_device.hpp"
 #include "bessel_internal.hpp"
 
 namespace bk {
 
-int logk_mlp(int64_t, const float*, const float*, const float*, float*, float*, float*, int, bool, const bessel_mlp*,
-             hipStream_t) {
-  return set_error(BESSEL_ERR_UNSUPPORTED, "learned range not built yet");
+constexpr int kH = 64;
+constexpr int kNW = BESSEL_MLP_NWEIGHTS;  // 4482
+constexpr int kNP = BESSEL_MLP_NPARAMS;   // 4490
+constexpr int oW1 = 0, ob1 = 128, oW2 = 192, ob2 = 4288, oW3 = 4352, ob3 = 4480, oMeta = 4482;
+constexpr float kVFloor = 1e-3f;
+constexpr float kMarginF32 = 15.9423851528787422f;  // -log 2^-23
+
+// ---------------------------------------------------------------------------
+// Shared device helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ void mlp_features(const float* __restrict__ P, float v, float x, float& z0, float& z1) {
+  const float lv = kLn2F * hlog2(fmaxf(fabsf(v), kVFloor));
+  const float lx = kLn2F * hlog2(x);
+  z0 = (lv - P[oMeta + 0]) / P[oMeta + 1];
+  z1 = (lx - P[oMeta + 2]) / P[oMeta + 3];
 }
 
-int range_mlp(int64_t, const float*, const float*, float*, float*, float*, float*, uint8_t*, const bessel_mlp*,
-              hipStream_t) {
-  return set_error(BESSEL_ERR_UNSUPPORTED, "learned range not built yet");
+// tanh from a pre-activation already scaled by 2 log2(e):  1 - 2 / (1 + 2^a).
+__device__ __forceinline__ float tanh_scaled(float a) {
+  return fmaf(-2.0f, hrcp(1.0f + hexp2(a)), 1.0f);
+}
+
+constexpr float k2Log2e = 2.88539008178f;  // 2 log2(e)
+
+// splitmix64 (Steele, Lea, Flood 2014): counter-based draws for minibatches.
+__device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
+  z += 0x9e3779b97f4a7c15ULL;
+  z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ULL;
+  z = (z ^ (z >> 27)) * 0x94d049bb133111ebULL;
+  return z ^ (z >> 31);
+}
+
+// ---------------------------------------------------------------------------
+// Labels: the Newton bracket at the FP32 margin.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_mlp_labels(int64_t n, const float* __restrict__ v,
+                                                       const float* __restrict__ x, float* __restrict__ t0,
+                                                       float* __restrict__ t1) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const Bracket b = find_bracket(fabs((double)v[i]), (double)x[i], kMarginF32);
+  t0[i] = b.t0;
+  t1[i] = b.t1;
+}
+
+// ---------------------------------------------------------------------------
+// Training: per-sample forward and backward (FP32), per-block partial
+// gradients, then a fixed-order reduction over blocks (deterministic).
+// One wavefront per block; the block's per-sample vectors are staged in LDS.
+// ---------------------------------------------------------------------------
+constexpr int kTB = 64;  // samples per training block (one wavefront)
+
+// Two staging phases keep the block's LDS under 64 KB: first the vectors of
+// the W2 / b2 / W1 / b1 gradients, then those of W3 / b3.
+struct TrainLds {
+  float a[kTB][kH + 1];  // +1 pad: column reads by sample hit distinct banks
+  float b[kTB][kH + 1];
+  float z[kTB][2];
+  float dy[kTB][2];
+  float loss[kTB];
+};
+
+// sampled: sample s of the step is index splitmix64(seed ^ step-key ^ s) mod n;
+// otherwise sample s is element s.  Partial gradients of block b go to
+// partial[b * (kNW + 1) .. + kNW), the partial loss to partial[b * (kNW + 1) + kNW].
+// Weights are read with block-uniform indices (scalar loads); the per-sample
+// vectors are fully unrolled into registers.
+__global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, int64_t n, int64_t batch,
+                                                  int sampled, uint64_t seed, int64_t step,
+                                                  const float* __restrict__ v, const float* __restrict__ x,
+                                                  const float* __restrict__ lt0, const float* __restrict__ lt1,
+                                                  float alpha, float* __restrict__ partial) {
+  __shared__ TrainLds S;
+  const int t = threadIdx.x;
+  const int64_t s = (int64_t)blockIdx.x * kTB + t;
+  const bool valid = s < batch;
+  int64_t idx = 0;
+  if (valid)
+    idx = sampled ? (int64_t)(splitmix64(seed ^ ((uint64_t)step * 0x100000001b3ULL) ^ (uint64_t)s) % (uint64_t)n) : s;
+  float z0 = 0.0f, z1 = 0.0f, dy0 = 0.0f, dy1 = 0.0f, lossv = 0.0f;
+  float h1[kH], h2[kH], d2[kH];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) h1[j] = 0.0f;
+#pragma unroll
+  for (int i = 0; i < kH; ++i) h2[i] = 0.0f;
+  if (valid) {
+    mlp_features(P, v[idx], x[idx], z0, z1);
+#pragma unroll
+    for (int j = 0; j < kH; ++j) h1[j] = tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])));
+#pragma unroll
+    for (int i = 0; i < kH; ++i) {
+      float a = P[ob2 + i];
+#pragma unroll
+      for (int j = 0; j < kH; ++j) a = fmaf(P[oW2 + i * kH + j], h1[j], a);
+      h2[i] = tanhf(a);
+    }
+    float y0 = P[ob3], y1 = P[ob3 + 1];
+#pragma unroll
+    for (int i = 0; i < kH; ++i) {
+      y0 = fmaf(P[oW3 + i], h2[i], y0);
+      y1 = fmaf(P[oW3 + kH + i], h2[i], y1);
+    }
+    const float T0 = lt0[idx], T1 = lt1[idx];
+    const float e0 = y0 - T0 / T1;
+    const float e1 = y1 - logf(T1);
+    const float w0 = e0 > 0.0f ? alpha : 1.0f;
+    const float w1 = e1 < 0.0f ? alpha : 1.0f;
+    const float inv_b = 1.0f / (float)batch;
+    lossv = 0.5f * (w0 * e0 * e0 + w1 * e1 * e1) * inv_b;
+    dy0 = w0 * e0 * inv_b;
+    dy1 = w1 * e1 * inv_b;
+  }
+  // backward through the two tanh layers (all zero for invalid samples)
+#pragma unroll
+  for (int i = 0; i < kH; ++i) d2[i] = fmaf(P[oW3 + i], dy0, P[oW3 + kH + i] * dy1) * (1.0f - h2[i] * h2[i]);
+  S.z[t][0] = z0;
+  S.z[t][1] = z1;
+  S.dy[t][0] = dy0;
+  S.dy[t][1] = dy1;
+  S.loss[t] = lossv;
+  // phase 1: d2 and h1 -> W2, b2; d1 and z -> W1, b1
+#pragma unroll
+  for (int i = 0; i < kH; ++i) S.a[t][i] = d2[i];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) S.b[t][j] = h1[j];
+  float d1[kH];
+#pragma unroll
+  for (int j = 0; j < kH; ++j) {
+    float a = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kH; ++i) a = fmaf(P[oW2 + i * kH + j], d2[i], a);
+    d1[j] = a * (1.0f - h1[j] * h1[j]);
+  }
+  __syncthreads();
+  float* out = partial + (int64_t)blockIdx.x * (kNW + 1);
+  for (int e = oW2 + t; e < oW3; e += kTB) {
+    float acc = 0.0f;
+    if (e < ob2) {  // W2[i][j]
+      const int i = (e - oW2) >> 6, j = (e - oW2) & 63;
+      for (int q = 0; q < kTB; ++q) acc = fmaf(S.a[q][i], S.b[q][j], acc);
+    } else {  // b2[i]
+      const int i = e - ob2;
+      for (int q = 0; q < kTB; ++q) acc += S.a[q][i];
+    }
+    out[e] = acc;
+  }
+  __syncthreads();
+  // phase 2: d1 -> W1, b1 (with z); h2 -> W3, b3 (with dy)
+#pragma unroll
+  for (int j = 0; j < kH; ++j) S.a[t][j] = d1[j];
+#pragma unroll
+  for (int i = 0; i < kH; ++i) S.b[t][i] = h2[i];
+  __syncthreads();
+  for (int e = t; e < kNW; e += kTB) {
+    if (e >= oW2 && e < oW3) continue;
+    float acc = 0.0f;
+    if (e < ob1) {  // W1[j][k]
+      const int j = e >> 1, k = e & 1;
+      for (int q = 0; q < kTB; ++q) acc = fmaf(S.a[q][j], S.z[q][k], acc);
+    } else if (e < oW2) {  // b1[j]
+      const int j = e - ob1;
+      for (int q = 0; q < kTB; ++q) acc += S.a[q][j];
+    } else if (e < ob3) {  // W3[o][i]
+      const int o = (e - oW3) >> 6, i = (e - oW3) & 63;
+      for (int q = 0; q < kTB; ++q) acc = fmaf(S.dy[q][o], S.b[q][i], acc);
+    } else {  // b3[o]
+      const int o = e - ob3;
+      for (int q = 0; q < kTB; ++q) acc += S.dy[q][o];
+    }
+    out[e] = acc;
+  }
+  if (t == 0) {
+    float l = 0.0f;
+    for (int q = 0; q < kTB; ++q) l += S.loss[q];
+    out[kNW] = l;
+  }
+}
+
+// grad[e] = sum over blocks of partial[b][e] in block order; loss likewise.
+__global__ __launch_bounds__(kBlock) void k_mlp_reduce(const float* __restrict__ partial, int nblocks,
+                                                       float* __restrict__ grad, float* __restrict__ loss) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e > kNW) return;
+  double acc = 0.0;
+  for (int b = 0; b < nblocks; ++b) acc += (double)partial[(int64_t)b * (kNW + 1) + e];
+  if (e < kNW) grad[e] = (float)acc;
+  else if (loss) *loss = (float)acc;
+}
+
+// Adam (Kingma & Ba) with bias correction; step counts from 1.
+__global__ __launch_bounds__(kBlock) void k_mlp_adam(float* __restrict__ P, const float* __restrict__ grad,
+                                                     float* __restrict__ m, float* __restrict__ s2, int64_t step,
+                                                     float lr, float beta1, float beta2, float eps) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= kNW) return;
+  const float g = grad[e];
+  const float mm = beta1 * m[e] + (1.0f - beta1) * g;
+  const float ss = beta2 * s2[e] + (1.0f - beta2) * g * g;
+  m[e] = mm;
+  s2[e] = ss;
+  const float mh = mm / (1.0f - powf(beta1, (float)step));
+  const float sh = ss / (1.0f - powf(beta2, (float)step));
+  P[e] -= lr * mh / (sqrtf(sh) + eps);
+}
+
+// ---------------------------------------------------------------------------
+// Inference
+// ---------------------------------------------------------------------------
+
+// FP32 reference forward, one element per lane, exact tanh (for parity tests).
+__global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restrict__ P, int64_t n,
+                                                            const float* __restrict__ v, const float* __restrict__ x,
+                                                            float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float z0, z1;
+  mlp_features(P, v[i], x[i], z0, z1);
+  float h1[kH];
+  for (int j = 0; j < kH; ++j) h1[j] = tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])));
+  float y0 = P[ob3], y1 = P[ob3 + 1];
+  for (int k = 0; k < kH; ++k) {
+    float a = P[ob2 + k];
+    for (int j = 0; j < kH; ++j) a = fmaf(P[oW2 + k * kH + j], h1[j], a);
+    const float h2 = tanhf(a);
+    y0 = fmaf(P[oW3 + k], h2, y0);
+    y1 = fmaf(P[oW3 + kH + k], h2, y1);
+  }
+  y[2 * i] = y0;
+  y[2 * i + 1] = y1;
+}
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+// One wavefront evaluates the network for its 64 elements (lane = element).
+// Layer 1 and the activations on the VALU; the 64 x 64 layer on
+// v_mfma_f32_16x16x32_bf16 with D[hidden out][element] = W2 * H1^T:
+//   A (16 x 32, weights): lane l holds row l%16, columns 8(l/16)..8(l/16)+7
+//   B (32 x 16, H1^T):    lane l holds column l%16, rows 8(l/16)..8(l/16)+7
+//   D (16 x 16):          lane l holds column l%16, rows 4(l/16)..4(l/16)+3
+// H1 travels through LDS (bf16, [element][hidden]) to reach the B layout;
+// the layer-3 dot products are finished with cross-lane sums over the four
+// lane groups.  Pre-activations are scaled by 2 log2(e) for tanh_scaled.
+// lds: 64 x 64 bf16 for this wave.  Returns y0, y1 for the lane's element.
+// Every thread of the block must call it (it contains a block barrier).
+__device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ P, float z0, float z1, __bf16* lds,
+                                              float& y0, float& y1) {
+  const int l = threadIdx.x & 63;
+  const int lr = l & 15, lg = l >> 4;
+  // layer 1 for this lane's element -> LDS row l
+#pragma unroll
+  for (int j0 = 0; j0 < kH; j0 += 8) {
+    bf16x8 pk;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int j = j0 + u;
+      const float a = k2Log2e * fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]));
+      pk[u] = (__bf16)tanh_scaled(a);
+    }
+    *reinterpret_cast<bf16x8*>(lds + l * kH + j0) = pk;
+  }
+  // weights of this lane's A fragments (scaled), and biases of its D rows
+  bf16x8 A[4][2];
+  f32x4 bias[4];
+#pragma unroll
+  for (int o = 0; o < 4; ++o) {
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int u = 0; u < 8; ++u)
+        A[o][kk][u] = (__bf16)(k2Log2e * P[oW2 + (16 * o + lr) * kH + 32 * kk + 8 * lg + u]);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) bias[o][r] = k2Log2e * P[ob2 + 16 * o + 4 * lg + r];
+  }
+  // layer-3 weights of this lane's D rows
+  float w30[16], w31[16];
+#pragma unroll
+  for (int o = 0; o < 4; ++o)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      w30[4 * o + r] = P[oW3 + 16 * o + 4 * lg + r];
+      w31[4 * o + r] = P[oW3 + kH + 16 * o + 4 * lg + r];
+    }
+  __syncthreads();  // H1 rows written by other lanes are read below
+  float p0[4], p1[4];
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const bf16x8 B0 = *reinterpret_cast<const bf16x8*>(lds + (16 * e + lr) * kH + 0 + 8 * lg);
+    const bf16x8 B1 = *reinterpret_cast<const bf16x8*>(lds + (16 * e + lr) * kH + 32 + 8 * lg);
+    float s0 = 0.0f, s1 = 0.0f;
+#pragma unroll
+    for (int o = 0; o < 4; ++o) {
+      f32x4 d = bias[o];
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[o][0], B0, d, 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[o][1], B1, d, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const float h2 = tanh_scaled(d[r]);
+        s0 = fmaf(w30[4 * o + r], h2, s0);
+        s1 = fmaf(w31[4 * o + r], h2, s1);
+      }
+    }
+    // sum the four lane groups holding the other hidden units of element 16e + lr
+    s0 += __shfl_xor(s0, 16);
+    s1 += __shfl_xor(s1, 16);
+    s0 += __shfl_xor(s0, 32);
+    s1 += __shfl_xor(s1, 32);
+    p0[e] = s0;
+    p1[e] = s1;
+  }
+  // lane l = 16 lg + lr owns element-tile lg
+  y0 = P[ob3] + (lg == 0 ? p0[0] : lg == 1 ? p0[1] : lg == 2 ? p0[2] : p0[3]);
+  y1 = P[ob3 + 1] + (lg == 0 ? p1[0] : lg == 1 ? p1[1] : lg == 2 ? p1[2] : p1[3]);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __restrict__ P, int64_t n,
+                                                             const float* __restrict__ v,
+                                                             const float* __restrict__ x, float* __restrict__ y) {
+  __shared__ __bf16 lds[kBlock / 64][64 * kH];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  float z0 = 0.0f, z1 = 0.0f;
+  if (i < n) mlp_features(P, v[i], x[i], z0, z1);
+  float y0, y1;
+  mlp_wave_mfma(P, z0, z1, lds[threadIdx.x >> 6], y0, y1);
+  if (i < n) {
+    y[2 * i] = y0;
+    y[2 * i + 1] = y1;
+  }
+}
+
+// g at one point for the shift of a learned bracket, FP32 hardware form.  Any finite shift is exact (log K = G + log(h S0) with S0 relative to
+// the same G); inside the bracket g >= max g - L, so the exponents stay below
+// L and FP32 cannot overflow.
+__device__ __forceinline__ float shift_at(float v, float x, float t) {
+  const float e = hexp2(kLog2eF * t);
+  return log_cosh_f32(v * t) - 0.5f * x * (e + hrcp(e));
+}
+
+// Acceptance of a learned bracket after its bins (all relative to e^{G}):
+//   coverage   the end terms are at most eps_32 (t0 = 0 needs no lower test);
+//              since G <= max g, this bounds g at the ends by max g + log eps;
+//   resolution the even-node and odd-node rules (step 2h) agree to 1e-5, so
+//              the full rule's error is far below FP32 resolution;
+//   finiteness of every sum.
+__device__ __forceinline__ bool accept_bins(const BinSums& s, float t0) {
+  const float tau = 1.1920929e-07f;
+  const bool cover = (t0 == 0.0f || s.term0 <= tau) && s.termN <= tau;
+  const bool resolved = fabs(s.Seven - s.Sodd) <= 1e-5 * 0.5 * (s.Seven + s.Sodd);
+  return cover && resolved && isfinite(s.S0) && s.S0 > 0.0;
+}
+
+// Fused: network (bf16 MFMA) -> bracket -> checked FP32 bins -> outputs, or the
+// element index onto the worklist (count at work[0], indices from work[1]).
+template <bool GRAD, int NB>
+__global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ P, int64_t n, int nbins,
+                                                     const float* __restrict__ vin, const float* __restrict__ xin,
+                                                     const float* __restrict__ gout, float* __restrict__ logk,
+                                                     float* __restrict__ dv, float* __restrict__ dx,
+                                                     float* __restrict__ t0o, float* __restrict__ t1o,
+                                                     float* __restrict__ tpo, float* __restrict__ gpo,
+                                                     uint8_t* __restrict__ fb, int* __restrict__ work) {
+  __shared__ __bf16 lds[kBlock / 64][64 * kH];
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  const int nb = NB > 0 ? NB : nbins;
+  const bool in = i < n;
+  const float vs = in ? vin[i] : 1.0f;
+  const float xf = in ? xin[i] : 1.0f;
+  double lk = 0.0, dvv = 0.0, dxv = 0.0;
+  const bool special = in && domain_special((double)vs, (double)xf, lk, dvv, dxv);
+  // the whole wavefront takes part in the network
+  float z0 = 0.0f, z1 = 0.0f;
+  if (in && !special) mlp_features(P, vs, xf, z0, z1);
+  float y0, y1;
+  mlp_wave_mfma(P, z0, z1, lds[threadIdx.x >> 6], y0, y1);
+  bool ok = true;
+  float t0 = 0.0f, t1 = 0.0f, G = 0.0f;
+  if (in && !special) {
+    const float v = fabsf(vs);
+    const float t1r = hexp2(kLog2eF * y1);  // predicted t1 before widening
+    t0 = fmaxf(0.0f, y0 - P[oMeta + 5]) * t1r;
+    t1 = t1r * hexp2(kLog2eF * P[oMeta + 4]);
+    // shift: the largest of g at the midpoint, at asinh(v/x) (the peak when
+    // v t_p >> 1, clamped into the bracket) and, for t0 = 0, g(0) = -x
+    const float r = fminf(v * hrcp(xf), 1e18f);
+    const float ta = fminf(fmaxf(kLn2F * hlog2(r + hsqrt(fmaf(r, r, 1.0f))), t0), t1);
+    G = fmaxf(shift_at(v, xf, 0.5f * (t0 + t1)), shift_at(v, xf, ta));
+    if (t0 == 0.0f) G = fmaxf(G, -xf);
+    ok = isfinite(t1) && t1 > t0 && isfinite(G);
+    if (ok) {
+      const BinSums s = bins_f32<GRAD, true>(nb, (double)v, (double)xf, (double)G, (double)t0, (double)t1);
+      ok = accept_bins(s, t0);
+      if (ok) {
+        const double h = ((double)t1 - (double)t0) / (double)nb;
+        const double rS0 = rcp_f64(s.S0);
+        lk = (double)G + log_f64(h * s.S0);
+        if (GRAD) {
+          dvv = (v == 0.0f) ? 0.0 : copysign(s.Sv * rS0, (double)vs);
+          dxv = -s.Sx * rS0;
+        }
+      }
+    }
+  }
+  // compaction of the failures: one atomic per wavefront
+  const bool fail = in && !special && !ok;
+  const unsigned long long mask = __ballot(fail);
+  if (mask) {
+    const int lane = threadIdx.x & 63;
+    const int leader = __ffsll((long long)mask) - 1;
+    int base = 0;
+    if (lane == leader) base = atomicAdd(work, __popcll(mask));
+    base = __shfl(base, leader);
+    if (fail) work[1 + base + __popcll(mask & ((1ULL << lane) - 1ULL))] = (int)i;
+  }
+  if (!in) return;
+  if (fb) fb[i] = fail ? 1 : 0;
+  if (fail) return;
+  if (logk) logk[i] = (float)lk;
+  if (GRAD) {
+    if (gout) {
+      const double go = (double)gout[i];
+      dvv *= go;
+      dxv *= go;
+    }
+    dv[i] = (float)dvv;
+    dx[i] = (float)dxv;
+  }
+  if (t0o) {
+    t0o[i] = special ? __builtin_nanf("") : t0;
+    t1o[i] = special ? __builtin_nanf("") : t1;
+    if (tpo) tpo[i] = special ? __builtin_nanf("") : 0.5f * (t0 + t1);
+    if (gpo) gpo[i] = special ? __builtin_nanf("") : G;
+  }
+}
+
+// Persistent fallback over the worklist: the Newton path of k_logk<float>,
+// element by element.  Every lane leaves when the list is exhausted.
+template <bool GRAD, int NB>
+__global__ __launch_bounds__(kBlock) void k_logk_fallback(int nbins, const int* __restrict__ work,
+                                                          const float* __restrict__ vin, const float* __restrict__ xin,
+                                                          const float* __restrict__ gout, float* __restrict__ logk,
+                                                          float* __restrict__ dv, float* __restrict__ dx,
+                                                          float* __restrict__ t0o, float* __restrict__ t1o,
+                                                          float* __restrict__ tpo, float* __restrict__ gpo) {
+  const int count = work[0];
+  const int nb = NB > 0 ? NB : nbins;
+  for (int k = blockIdx.x * kBlock + threadIdx.x; k < count; k += gridDim.x * kBlock) {
+    const int64_t i = work[1 + k];
+    const double vs = (double)vin[i];
+    const double x = (double)xin[i];
+    const double v = fabs(vs);
+    const Bracket b = find_bracket(v, x, kMarginF32);
+    if (t0o) {
+      t0o[i] = b.t0;
+      t1o[i] = b.t1;
+      if (tpo) tpo[i] = b.tp;
+      if (gpo) gpo[i] = (float)b.G;
+      if (!logk && !dv) continue;
+    }
+    const BinSums s = bins_f32<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+    const double rS0 = rcp_f64(s.S0);
+    if (logk) logk[i] = (float)(b.G + log_f64(h * s.S0));
+    if (GRAD) {
+      double dvv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
+      double dxv = -s.Sx * rS0;
+      if (gout) {
+        const double go = (double)gout[i];
+        dvv *= go;
+        dxv *= go;
+      }
+      dv[i] = (float)dvv;
+      dx[i] = (float)dxv;
+    }
+  }
+}
+
+__global__ void k_zero_int(int* p) { *p = 0; }
+
+}  // namespace bk
+
+// ---------------------------------------------------------------------------
+// Handle
+// ---------------------------------------------------------------------------
+struct bessel_mlp {
+  float* params = nullptr;  // [kNP]
+  float* adam_m = nullptr;  // [kNW]
+  float* adam_s = nullptr;  // [kNW]
+  float* grad = nullptr;    // [kNW + 1] (last: loss)
+  float* partial = nullptr;
+  int64_t cap_partial_blocks = 0;
+  float* labels = nullptr;  // [2 * cap_labels]
+  int64_t cap_labels = 0;
+  float* losses = nullptr;  // [cap_losses]
+  int64_t cap_losses = 0;
+  int* work = nullptr;  // [1 + cap_work]
+  int64_t cap_work = 0;
+  int64_t adam_step = 0;
+};
+
+using namespace bk;
+
+namespace {
+
+int hip_fail(hipError_t e, const char* what) {
+  return set_error(BESSEL_ERR_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+// Grow a device buffer (contents not preserved).  Stream-ordered so the hot
+// path never synchronises; the old buffer is released after prior work.
+template <typename T>
+int ensure(T*& p, int64_t& cap, int64_t need, hipStream_t st, const char* what) {
+  if (need <= cap && p) return BESSEL_OK;
+  if (p) {
+    hipError_t e = hipFreeAsync(p, st);
+    if (e != hipSuccess) return hip_fail(e, what);
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t e = hipMallocAsync((void**)&p, (size_t)need * sizeof(T), st);
+  if (e != hipSuccess) return hip_fail(e, what);
+  cap = need;
+  return BESSEL_OK;
+}
+
+}  // namespace
+
+extern "C" int bessel_mlp_create(const float* params, int64_t nparams, bessel_mlp** out) {
+  if (!out) return set_error(BESSEL_ERR_ARG, "out must be non-NULL");
+  *out = nullptr;
+  if (params && nparams != kNP) return set_error(BESSEL_ERR_ARG, "nparams must be %d", kNP);
+  bessel_mlp* m = new (std::nothrow) bessel_mlp();
+  if (!m) return set_error(BESSEL_ERR_ARG, "out of host memory");
+  hipError_t e = hipMalloc((void**)&m->params, kNP * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->adam_m, kNW * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->adam_s, kNW * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->grad, (kNW + 1) * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->adam_m, 0, kNW * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->adam_s, 0, kNW * sizeof(float));
+  if (e == hipSuccess) {
+    if (params) {
+      e = hipMemcpy(m->params, params, kNP * sizeof(float), hipMemcpyHostToDevice);
+    } else {
+      float host[kNP];
+      memset(host, 0, sizeof(host));
+      host[oMeta + 1] = 1.0f;
+      host[oMeta + 3] = 1.0f;
+      e = hipMemcpy(m->params, host, sizeof(host), hipMemcpyHostToDevice);
+    }
+  }
+  if (e != hipSuccess) {
+    int rc = hip_fail(e, "bessel_mlp_create");
+    bessel_mlp_destroy(m);
+    return rc;
+  }
+  *out = m;
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_mlp_destroy(bessel_mlp* m) {
+  if (!m) return BESSEL_OK;
+  (void)hipDeviceSynchronize();
+  void* sync_ptrs[] = {m->params, m->adam_m, m->adam_s, m->grad};
+  for (void* p : sync_ptrs)
+    if (p) (void)hipFree(p);
+  void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work};  // from hipMallocAsync
+  for (void* p : async_ptrs)
+    if (p) (void)hipFreeAsync(p, nullptr);
+  (void)hipDeviceSynchronize();
+  delete m;
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_mlp_set_params(bessel_mlp* m, const float* params, int64_t nparams) {
+  if (!m || !params) return set_error(BESSEL_ERR_ARG, "mlp and params must be non-NULL");
+  if (nparams != kNP) return set_error(BESSEL_ERR_ARG, "nparams must be %d", kNP);
+  hipError_t e = hipMemcpy(m->params, params, kNP * sizeof(float), hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemset(m->adam_m, 0, kNW * sizeof(float));
+  if (e == hipSuccess) e = hipMemset(m->adam_s, 0, kNW * sizeof(float));
+  if (e != hipSuccess) return hip_fail(e, "bessel_mlp_set_params");
+  m->adam_step = 0;
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_mlp_get_params(const bessel_mlp* m, float* params, int64_t nparams) {
+  if (!m || !params) return set_error(BESSEL_ERR_ARG, "mlp and params must be non-NULL");
+  if (nparams != kNP) return set_error(BESSEL_ERR_ARG, "nparams must be %d", kNP);
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(params, m->params, kNP * sizeof(float), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "bessel_mlp_get_params");
+  return BESSEL_OK;
+}
+
+static int launch_grad(bessel_mlp* m, int64_t n, int64_t batch, int sampled, uint64_t seed, int64_t step,
+                       const float* v, const float* x, const float* t0, const float* t1, float alpha,
+                       hipStream_t st) {
+  const int64_t nblocks = (batch + kTB - 1) / kTB;
+  int rc = ensure(m->partial, m->cap_partial_blocks, nblocks * (kNW + 1), st, "partial gradients");
+  if (rc) return rc;
+  k_mlp_grad<<<dim3((unsigned)nblocks), kTB, 0, st>>>(m->params, n, batch, sampled, seed, step, v, x, t0, t1,
+                                                      alpha, m->partial);
+  k_mlp_reduce<<<dim3((kNW + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->partial, (int)nblocks, m->grad,
+                                                                        m->grad + kNW);
+  return check_launch("k_mlp_grad");
+}
+
+extern "C" int bessel_mlp_loss_grad(bessel_mlp* m, int64_t n, const float* v, const float* x, const float* t0,
+                                    const float* t1, float alpha, float* loss, float* grad, void* hip_stream) {
+  if (!m || !v || !x || !t0 || !t1 || !loss || !grad) return set_error(BESSEL_ERR_ARG, "NULL argument");
+  if (n <= 0 || n > (1LL << 30)) return set_error(BESSEL_ERR_ARG, "n = %lld outside [1, 2^30]", (long long)n);
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = launch_grad(m, n, n, 0, 0, 0, v, x, t0, t1, alpha, st);
+  if (rc) return rc;
+  hipError_t e = hipMemcpyAsync(grad, m->grad, kNW * sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e == hipSuccess) e = hipMemcpyAsync(loss, m->grad + kNW, sizeof(float), hipMemcpyDeviceToDevice, st);
+  if (e != hipSuccess) return hip_fail(e, "bessel_mlp_loss_grad");
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_mlp_train(bessel_mlp* m, const bessel_mlp_train_cfg* cfg, int64_t n, const float* v,
+                                const float* x, float* loss_host, void* hip_stream) {
+  if (!m || !cfg || !v || !x) return set_error(BESSEL_ERR_ARG, "NULL argument");
+  if (n <= 0 || n > (1LL << 30)) return set_error(BESSEL_ERR_ARG, "n = %lld outside [1, 2^30]", (long long)n);
+  if (cfg->steps < 0 || cfg->batch <= 0 || cfg->batch > (1LL << 24))
+    return set_error(BESSEL_ERR_ARG, "steps must be >= 0 and batch in [1, 2^24]");
+  hipStream_t st = (hipStream_t)hip_stream;
+  int rc = ensure(m->labels, m->cap_labels, 2 * n, st, "labels");
+  if (rc) return rc;
+  rc = ensure(m->losses, m->cap_losses, cfg->steps > 0 ? cfg->steps : 1, st, "losses");
+  if (rc) return rc;
+  float* t0 = m->labels;
+  float* t1 = m->labels + n;
+  dim3 grid;
+  rc = grid_for(n, grid);
+  if (rc) return rc;
+  k_mlp_labels<<<grid, kBlock, 0, st>>>(n, v, x, t0, t1);
+  rc = check_launch("k_mlp_labels");
+  if (rc) return rc;
+  for (int64_t k = 0; k < cfg->steps; ++k) {
+    rc = launch_grad(m, n, cfg->batch, 1, cfg->seed, k, v, x, t0, t1, cfg->alpha, st);
+    if (rc) return rc;
+    hipError_t e = hipMemcpyAsync(m->losses + k, m->grad + kNW, sizeof(float), hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) return hip_fail(e, "loss copy");
+    // exponential decay from lr to lr_final over the run
+    const double frac = cfg->steps > 1 ? (double)k / (double)(cfg->steps - 1) : 0.0;
+    const float lr = (float)(cfg->lr * pow((double)cfg->lr_final / (double)cfg->lr, frac));
+    m->adam_step += 1;
+    k_mlp_adam<<<dim3((kNW + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->params, m->grad, m->adam_m, m->adam_s,
+                                                                     m->adam_step, lr, cfg->beta1, cfg->beta2,
+                                                                     cfg->adam_eps);
+    rc = check_launch("k_mlp_adam");
+    if (rc) return rc;
+  }
+  if (loss_host && cfg->steps > 0) {
+    hipError_t e = hipMemcpyAsync(loss_host, m->losses, cfg->steps * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return hip_fail(e, "loss readback");
+  }
+  return BESSEL_OK;
+}
+
+extern "C" int bessel_mlp_adam_step(bessel_mlp* m, const float* grad, float lr, float beta1, float beta2, float eps,
+                                    void* hip_stream) {
+  if (!m || !grad) return set_error(BESSEL_ERR_ARG, "NULL argument");
+  hipStream_t st = (hipStream_t)hip_stream;
+  m->adam_step += 1;
+  k_mlp_adam<<<dim3((kNW + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->params, grad, m->adam_m, m->adam_s,
+                                                                   m->adam_step, lr, beta1, beta2, eps);
+  return check_launch("k_mlp_adam");
+}
+
+extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v, const float* x, float* y, int mode,
+                                  void* hip_stream) {
+  if (!m || (n > 0 && (!v || !x || !y))) return set_error(BESSEL_ERR_ARG, "NULL argument");
+  if (mode != 0 && mode != 1) return set_error(BESSEL_ERR_ARG, "mode must be 0 (FP32) or 1 (bf16 MFMA)");
+  if (n == 0) return BESSEL_OK;
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (mode == 0)
+    k_mlp_forward_f32<<<grid, kBlock, 0, st>>>(m->params, n, v, x, y);
+  else
+    k_mlp_forward_mfma<<<grid, kBlock, 0, st>>>(m->params, n, v, x, y);
+  return check_launch("k_mlp_forward");
+}
+
+namespace bk {
+
+// Fused learned-range pass + fallback (shared by logk, logk_dv_dx and range).
+template <bool GRAD>
+static int run_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx,
+                   float* t0, float* t1, float* tp, float* gp, uint8_t* fb, int nbins, const bessel_mlp* mc,
+                   hipStream_t st) {
+  bessel_mlp* m = const_cast<bessel_mlp*>(mc);
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  if (n > 0x7fffffffLL - 1) return set_error(BESSEL_ERR_ARG, "n too large for the learned-range worklist");
+  rc = ensure(m->work, m->cap_work, n + 1, st, "worklist");
+  if (rc) return rc;
+  k_zero_int<<<1, 1, 0, st>>>(m->work);
+  switch (nbins) {
+    case 64:
+      k_logk_mlp<GRAD, 64><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+                                                    m->work);
+      break;
+    case 128:
+      k_logk_mlp<GRAD, 128><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+                                                     m->work);
+      break;
+    case 256:
+      k_logk_mlp<GRAD, 256><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+                                                     m->work);
+      break;
+    default:
+      k_logk_mlp<GRAD, 0><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+                                                   m->work);
+      break;
+  }
+  rc = check_launch("k_logk_mlp");
+  if (rc) return rc;
+  // persistent fallback grid: 4 blocks per CU
+  const dim3 fgrid(1024);
+  switch (nbins) {
+    case 64:
+      k_logk_fallback<GRAD, 64><<<fgrid, kBlock, 0, st>>>(nbins, m->work, v, x, go, lk, dv, dx, t0, t1, tp, gp);
+      break;
+    case 128:
+      k_logk_fallback<GRAD, 128><<<fgrid, kBlock, 0, st>>>(nbins, m->work, v, x, go, lk, dv, dx, t0, t1, tp, gp);
+      break;
+    case 256:
+      k_logk_fallback<GRAD, 256><<<fgrid, kBlock, 0, st>>>(nbins, m->work, v, x, go, lk, dv, dx, t0, t1, tp, gp);
+      break;
+    default:
+      k_logk_fallback<GRAD, 0><<<fgrid, kBlock, 0, st>>>(nbins, m->work, v, x, go, lk, dv, dx, t0, t1, tp, gp);
+      break;
+  }
+  return check_launch("k_logk_fallback");
+}
+
+int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
+             bool grad, const bessel_mlp* mlp, hipStream_t st) {
+  if (grad) return run_mlp<true>(n, v, x, go, lk, dv, dx, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp, st);
+  return run_mlp<false>(n, v, x, nullptr, lk, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp,
+                        st);
+}
+
+int range_mlp(int64_t n, const float* v, const float* x, float* t0, float* t1, float* tp, float* gpk,
+              uint8_t* fallback, const bessel_mlp* mlp, hipStream_t st) {
+  return run_mlp<false>(n, v, x, nullptr, nullptr, nullptr, nullptr, t0, t1, tp, gpk, fallback, 128, mlp, st);
 }
 
 }  // namespace bk
+
+extern "C" int bessel_mlp_fallback_count(const bessel_mlp* m, int* count_host) {
+  if (!m || !count_host) return set_error(BESSEL_ERR_ARG, "NULL argument");
+  if (!m->work) {
+    *count_host = 0;
+    return BESSEL_OK;
+  }
+  hipError_t e = hipDeviceSynchronize();
+  if (e == hipSuccess) e = hipMemcpy(count_host, m->work, sizeof(int), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(e, "bessel_mlp_fallback_count");
+  return BESSEL_OK;
+}

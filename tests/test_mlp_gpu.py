@@ -1,0 +1,220 @@
+"""GPU tests of the learned bracket predictor (through the C ABI).
+
+* training gradients and the Adam step against the FP64 reference (oracle/mlp_ref.py);
+* FP32 and bf16-MFMA inference against the reference forward;
+* a trained predictor's log K against the CPU oracle, with its fallback rate;
+* forced fallbacks (from the host: weights that make every check fail) give
+  outputs bitwise equal to the Newton path;
+* learned brackets that pass the check contain the exact truncation set.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import workloads
+from oracle import mlp_ref as R
+
+pytestmark = pytest.mark.gpu
+
+LOG_EPS32 = float(np.log(2.0 ** -23))
+
+
+@pytest.fixture(scope="module")
+def mods():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2108_11560_amd as bk
+    from paper_2108_11560_amd import mlp as M
+    bk.load()
+    return bk, M
+
+
+def dev32(a):
+    return torch.tensor(np.asarray(a), dtype=torch.float32, device="cuda")
+
+
+def host(t):
+    return t.double().cpu().numpy()
+
+
+def norm_of(p):
+    return tuple(float(a) for a in p[R.NPARAMS:R.NPARAMS + 4])
+
+
+def random_params(M, seed):
+    p = M.glorot_params(seed)
+    rng = np.random.default_rng(seed + 100)
+    # non-zero biases so every parameter block gets a gradient
+    p[128:192] = rng.normal(0, 0.3, 64)
+    p[4288:4352] = rng.normal(0, 0.3, 64)
+    p[4480:4482] = rng.normal(0, 0.3, 2)
+    return p
+
+
+def test_gradient_matches_fp64_reference(mods):
+    bk, M = mods
+    p = random_params(M, 1)
+    mlp = M.RangeMLP(p)
+    v, x, _ = workloads.scale_pairs(3000, seed=401)
+    v32, x32 = v.astype(np.float32), x.astype(np.float32)
+    # targets: the exact FP32-margin bracket from the oracle
+    _, _, t0, t1 = oracle.range_exact(v32.astype(np.float64), x32.astype(np.float64), LOG_EPS32)
+    loss, grad = mlp.loss_grad(dev32(v32), dev32(x32), dev32(t0), dev32(t1), alpha=4.0)
+    z = R.features(v32.astype(np.float64), x32.astype(np.float64), norm_of(p))
+    ystar = R.targets(t0.astype(np.float32).astype(np.float64), t1.astype(np.float32).astype(np.float64))
+    L, g = R.loss_and_grad(p[:R.NPARAMS].astype(np.float64), z, ystar, 4.0)
+    assert abs(float(loss) - L) <= 1e-5 * abs(L)
+    g_gpu = host(grad)
+    assert np.linalg.norm(g_gpu - g) <= 1e-4 * np.linalg.norm(g)
+    assert np.max(np.abs(g_gpu - g)) <= 1e-4 * np.max(np.abs(g))
+    mlp.close()
+
+
+def test_adam_step_matches_reference(mods):
+    bk, M = mods
+    p = random_params(M, 2)
+    mlp = M.RangeMLP(p)
+    rng = np.random.default_rng(5)
+    pr = p[:R.NPARAMS].astype(np.float64)
+    m = np.zeros(R.NPARAMS)
+    s = np.zeros(R.NPARAMS)
+    for step in range(1, 4):
+        g = rng.normal(0, 1e-2, R.NPARAMS)
+        mlp.adam_step(dev32(g), 1e-3)
+        pr, m, s = R.adam_step(pr, g.astype(np.float32).astype(np.float64), m, s, step, 1e-3)
+    got = mlp.params()[:R.NPARAMS].astype(np.float64)
+    assert np.max(np.abs(got - pr)) <= 2e-6
+    mlp.close()
+
+
+def test_forward_fp32_and_mfma(mods):
+    bk, M = mods
+    p = random_params(M, 3)
+    mlp = M.RangeMLP(p)
+    v, x, _ = workloads.scale_pairs(4097, seed=402)  # ragged: not a multiple of 64
+    vt, xt = dev32(v), dev32(x)
+    z = R.features(host(vt), host(xt), norm_of(p))
+    yref, _ = R.forward(p[:R.NPARAMS].astype(np.float64), z)
+    y32 = host(mlp.forward(vt, xt, mode=0))
+    assert np.max(np.abs(y32 - yref)) <= 2e-5
+    ymf = host(mlp.forward(vt, xt, mode=1))
+    # bf16 operands of the 64 x 64 layer: ~3 significant digits
+    assert np.max(np.abs(ymf - yref)) <= 3e-2 * max(1.0, np.max(np.abs(yref)))
+    mlp.close()
+
+
+def test_training_reduces_loss(mods):
+    bk, M = mods
+    mlp = M.RangeMLP(M.glorot_params(4))
+    v, x, _ = workloads.scale_pairs(1 << 16, seed=4)
+    losses = mlp.train(dev32(v), dev32(x), steps=400, batch=4096, lr=3e-3, lr_final=3e-4, seed=7)
+    assert np.all(np.isfinite(losses))
+    assert losses[-50:].mean() <= 0.05 * losses[:10].mean()
+    mlp.close()
+
+
+@pytest.fixture(scope="module")
+def trained(mods):
+    bk, M = mods
+    mlp = M.RangeMLP(M.glorot_params(0))
+    v, x, _ = workloads.scale_pairs(1 << 18, seed=4)
+    mlp.train(dev32(v), dev32(x), steps=20000, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
+    vc, xc, _ = workloads.scale_pairs(1 << 16, seed=8)
+    m1, m0, rate = M.calibrate_margins(mlp, dev32(vc), dev32(xc), target_fallback=0.005)
+    yield mlp, (m1, m0, rate)
+    mlp.close()
+
+
+@pytest.mark.parametrize("nbins", [64, 128, 256])
+def test_learned_range_parity(mods, trained, nbins):
+    bk, M = mods
+    mlp, (m1, m0, rate) = trained
+    v, x, strata = workloads.scale_pairs(1 << 20, seed=1)
+    idx = workloads.stratified_subset(strata, 1 << 13, seed=11)
+    vt, xt = dev32(v), dev32(x)
+    lk = bk.logk(vt, xt, nbins=nbins, range="mlp", mlp=mlp)
+    n_fb = mlp.fallback_count()
+    assert n_fb <= 0.02 * v.size
+    ref = oracle.logk(host(vt)[idx], host(xt)[idx])
+    err = np.abs(host(lk)[idx] - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-5
+    _, dv, dx = bk.logk_dv_dx(vt, xt, nbins=nbins, range="mlp", mlp=mlp)
+    _, rdv, rdx = oracle.logk(host(vt)[idx], host(xt)[idx], deriv=True)
+    assert (np.abs(host(dv)[idx] - rdv) / np.maximum(1.0, np.abs(rdv))).max() <= 1e-5
+    assert (np.abs(host(dx)[idx] - rdx) / np.maximum(1.0, np.abs(rdx))).max() <= 1e-5
+
+
+def test_learned_brackets_contain_exact_set(mods, trained):
+    bk, M = mods
+    mlp, _ = trained
+    v, x, _ = workloads.scale_pairs(1 << 14, seed=403)
+    vt, xt = dev32(v), dev32(x)
+    t0, t1, tp, G, fb = bk.bessel_range(vt, xt, range="mlp", mlp=mlp, want_fallback=True)
+    fb = host(fb).astype(bool)
+    assert mlp.fallback_count() == int(fb.sum())
+    _, _, e0, e1 = oracle.range_exact(host(vt), host(xt), LOG_EPS32)
+    t0, t1 = host(t0), host(t1)
+    assert np.all(t0 <= e0 + 1e-6 * (1 + e0))
+    assert np.all(t1 >= e1 - 1e-6 * (1 + e1))
+    # the fallback lanes carry the Newton bracket
+    n0, n1, _, _ = bk.bessel_range(vt, xt)
+    assert np.array_equal(t0[fb], host(n0)[fb]) and np.array_equal(t1[fb], host(n1)[fb])
+
+
+def test_forced_fallback_is_bitwise_newton(mods):
+    bk, M = mods
+    v, x, _ = workloads.scale_pairs(5000, seed=404)
+    vt, xt = dev32(v), dev32(x)
+    newton = bk.logk(vt, xt, nbins=128)
+    nl, ndv, ndx = bk.logk_dv_dx(vt, xt, nbins=128)
+    # zero weights with a large negative t1 margin: t1 = e^{-30}, every check fails
+    p = np.zeros(M.NPARAMS, dtype=np.float32)
+    p[M.O_META:M.O_META + 6] = [1.0, 3.0, 0.0, 4.0, -30.0, 0.0]
+    mlp = M.RangeMLP(p)
+    out = bk.logk(vt, xt, nbins=128, range="mlp", mlp=mlp)
+    assert mlp.fallback_count() == v.size
+    assert torch.equal(out, newton)
+    l2, dv, dx = bk.logk_dv_dx(vt, xt, nbins=128, range="mlp", mlp=mlp)
+    assert torch.equal(dv, ndv) and torch.equal(dx, ndx) and torch.equal(l2, nl)
+    # NaN weights: every check fails as well
+    p[:M.NWEIGHTS] = np.nan
+    mlp.set_params(p)
+    out = bk.logk(vt, xt, nbins=128, range="mlp", mlp=mlp)
+    assert mlp.fallback_count() == v.size
+    assert torch.equal(out, newton)
+    mlp.close()
+
+
+def test_learned_range_domain_conventions(mods, trained):
+    bk, M = mods
+    mlp, _ = trained
+    nan, inf = float("nan"), float("inf")
+    v = dev32([nan, 1.0, 1.0, 1.0, 1.0, inf, 2.5, -2.5])
+    x = dev32([1.0, nan, -1.0, 0.0, inf, 2.0, 3.0, 3.0])
+    lk = host(bk.logk(v, x, range="mlp", mlp=mlp))
+    assert np.isnan(lk[:3]).all()
+    assert lk[3] == np.inf and lk[4] == -np.inf and lk[5] == np.inf
+    assert lk[6] == lk[7]
+
+
+def test_checkpoint_roundtrip(mods, trained, tmp_path):
+    bk, M = mods
+    mlp, _ = trained
+    path = str(tmp_path / "mlp.npy")
+    mlp.save(path)
+    again = M.RangeMLP.load_file(path)
+    assert np.array_equal(again.params(), mlp.params())
+    v, x, _ = workloads.scale_pairs(4096, seed=405)
+    vt, xt = dev32(v), dev32(x)
+    assert torch.equal(bk.logk(vt, xt, range="mlp", mlp=mlp), bk.logk(vt, xt, range="mlp", mlp=again))
+    again.close()
+
+
+def test_mlp_rejects_f64(mods, trained):
+    bk, M = mods
+    mlp, _ = trained
+    v = torch.ones(4, dtype=torch.float64, device="cuda")
+    with pytest.raises(bk.BesselError):
+        bk.logk(v, v, range="mlp", mlp=mlp)
