@@ -184,6 +184,25 @@ int bessel_mlp_forward(const bessel_mlp* mlp, int64_t n, const float* v, const f
  * the Newton bracket (synchronises the device). */
 int bessel_mlp_fallback_count(const bessel_mlp* mlp, int* count);
 
+/*
+ * bessel_gh_logk_sum -- per-set sums over shared samples (FP32 arrays):
+ *   for set i (lam, alpha, delta, mu: [nsets]) and samples y[nsamp],
+ *     v = lam_i - 1/2,  r_j = sqrt(delta_i^2 + (y_j - mu_i)^2),  x_j = alpha_i r_j,
+ *     sum[i] = sum_j log K_v(x_j),
+ *   and the gradient of sum[i] with respect to lam_i, alpha_i, delta_i, mu_i
+ *   (each nullable), multiplied by grad_sum[i] when grad_sum is not NULL.
+ * This is the Bessel factor of a generalised-hyperbolic log-likelihood (the
+ * application named in the paper's introduction), evaluated with the FP32
+ * path and its derivatives (Sections 2 and 4.1) and the chain rule.  Sums are
+ * accumulated in FP64 and reduced in a fixed order (deterministic).  The call
+ * allocates a temporary of nsets * ceil(nsamp/256) * 5 doubles, stream-ordered
+ * on hip_stream.  range_mode must be BESSEL_RANGE_NEWTON.
+ */
+int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
+                       int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam,
+                       float* g_alpha, float* g_delta, float* g_mu, int nbins, int range_mode,
+                       const bessel_mlp* mlp, void* hip_stream);
+
 /* Message of the last failed call on the calling thread ("" if none). */
 const char* bessel_last_error(void);
 

@@ -32,6 +32,7 @@ __all__ = [
     "logk_dv_dx",
     "bessel_range",
     "log_bessel_k",
+    "gh_logk_sum",
     "BesselLogK",
     "BesselError",
     "load",
@@ -124,6 +125,31 @@ def bessel_range(v: torch.Tensor, x: torch.Tensor, range: str = "newton", mlp=No
                               _range_code(range), _mlp_ptr(mlp), _ptr(fb), _stream_ptr(v.device))
     check(rc, "bessel_range")
     return (t0, t1, tp, gp, fb) if want_fallback else (t0, t1, tp, gp)
+
+
+def gh_logk_sum(lam: torch.Tensor, alpha: torch.Tensor, delta: torch.Tensor, mu: torch.Tensor, y: torch.Tensor,
+                grad_sum: torch.Tensor | None = None, nbins: int = 128, want_grad: bool = True):
+    """Per-set sums of log K_{lam-1/2}(alpha sqrt(delta^2 + (y - mu)^2)) over the shared
+    samples y, and (optionally) their gradients in (lam, alpha, delta, mu), FP32."""
+    sets = [t.contiguous() for t in (lam, alpha, delta, mu)]
+    y = y.contiguous()
+    for t in (*sets, y) + ((grad_sum,) if grad_sum is not None else ()):
+        if t.dtype != torch.float32 or t.device.type != "cuda":
+            raise TypeError("gh_logk_sum takes float32 CUDA tensors")
+    n = sets[0].numel()
+    if any(t.numel() != n for t in sets) or (grad_sum is not None and grad_sum.numel() != n):
+        raise ValueError("lam, alpha, delta, mu (and grad_sum) must have the same length")
+    dev = y.device
+    out = torch.empty(n, dtype=torch.float32, device=dev)
+    grads = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)] if want_grad else [None] * 4
+    gs = grad_sum.contiguous() if grad_sum is not None else None
+    lib = load()
+    with torch.cuda.device(dev):
+        rc = lib.bessel_gh_logk_sum(n, *(_ptr(t) for t in sets), y.numel(), _ptr(y), _ptr(gs), _ptr(out),
+                                    *(_ptr(g) for g in grads), int(nbins), RANGE_NEWTON, ctypes.c_void_p(0),
+                                    _stream_ptr(dev))
+    check(rc, "bessel_gh_logk_sum")
+    return (out, *grads) if want_grad else out
 
 
 class BesselLogK(torch.autograd.Function):

@@ -46,6 +46,8 @@ SIGNATURES = {
     "bessel_mlp_forward": (_int, [_vp, _i64, _vp, _vp, _vp, _int, _vp]),
     "bessel_mlp_adam_step": (_int, [_vp, _vp, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float, _vp]),
     "bessel_mlp_fallback_count": (_int, [_vp, _vp]),
+    "bessel_gh_logk_sum": (_int, [_i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _int,
+                                  _vp, _vp]),
     "bessel_last_error": (ctypes.c_char_p, []),
     "bessel_version": (ctypes.c_char_p, []),
 }

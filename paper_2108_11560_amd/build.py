@@ -18,7 +18,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbessel.so")
 
-SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip"]
+SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip", "bessel_gh.hip"]
 
 ARCH = "gfx950"
 

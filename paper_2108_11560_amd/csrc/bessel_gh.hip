@@ -1,0 +1,153 @@
+// bessel_gh.hip -- per-set sums of log K over shared samples, with the
+// gradients of each sum with respect to the set's parameters.
+//
+// For set i with parameters (lambda, alpha, delta, mu) and samples y_j:
+//   v = lambda - 1/2,  r_j = sqrt(delta^2 + (y_j - mu)^2),  x_j = alpha r_j,
+//   S_i = sum_j log K_v(x_j)
+// (the shape of a generalised-hyperbolic log-likelihood, whose Bessel factor
+// motivates the method in the paper's introduction).  Each (i, j) runs the
+// FP32 path with derivatives (Sections 2 and 4.1); the chain rule gives
+//   dS/dlambda = sum dv,  dS/dalpha = sum dx r,  dS/ddelta = sum dx alpha delta / r,
+//   dS/dmu = sum dx alpha (mu - y) / r.
+// One block per (set, chunk of kBlock samples): wavefront shuffle sums and an
+// LDS sum give one FP64 partial per block; a second kernel adds the partials
+// of each set in chunk order (deterministic).
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "bessel.h"
+#include "bessel_device.hpp"
+#include "bessel_internal.hpp"
+
+namespace bk {
+
+constexpr int kGhQ = 5;  // sum, d/dlambda, d/dalpha, d/ddelta, d/dmu
+constexpr float kMarginGh = 15.9423851528787422f;  // FP32 eps
+
+__device__ __forceinline__ double wave_sum(double a) {
+#pragma unroll
+  for (int m = 32; m >= 1; m >>= 1) a += __shfl_xor(a, m);
+  return a;
+}
+
+template <int NB>
+__global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nchunks, int nbins,
+                                                       const float* __restrict__ lam, const float* __restrict__ alpha,
+                                                       const float* __restrict__ delta, const float* __restrict__ mu,
+                                                       const float* __restrict__ y, double* __restrict__ partial) {
+  __shared__ double red[kBlock / 64][kGhQ];
+  const int64_t set = (int64_t)blockIdx.x / nchunks;
+  const int64_t chunk = (int64_t)blockIdx.x - set * nchunks;
+  const int64_t j = chunk * kBlock + threadIdx.x;
+  const int nb = NB > 0 ? NB : nbins;
+  double c[kGhQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  if (j < nsamp) {
+    const double vs = (double)lam[set] - 0.5;
+    const double a = (double)alpha[set], d = (double)delta[set], m = (double)mu[set];
+    const double dy = (double)y[j] - m;
+    const double r = sqrt(fma(d, d, dy * dy));
+    const double x = a * r;
+    double lk, dv, dx;
+    if (!domain_special(vs, x, lk, dv, dx)) {
+      const double v = fabs(vs);
+      const Bracket b = find_bracket(v, x, kMarginGh);
+      const BinSums s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+      const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+      const double rS0 = rcp_f64(s.S0);
+      lk = b.G + log_f64(h * s.S0);
+      dv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
+      dx = -s.Sx * rS0;
+    }
+    const double rr = rcp_f64(r);
+    c[0] = lk;
+    c[1] = dv;
+    c[2] = dx * r;
+    c[3] = dx * a * d * rr;
+    c[4] = -dx * a * dy * rr;
+  }
+  const int w = threadIdx.x >> 6;
+#pragma unroll
+  for (int q = 0; q < kGhQ; ++q) {
+    const double s = wave_sum(c[q]);
+    if ((threadIdx.x & 63) == 0) red[w][q] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x < kGhQ) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < kBlock / 64; ++k) s += red[k][threadIdx.x];
+    partial[(int64_t)blockIdx.x * kGhQ + threadIdx.x] = s;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_gh_final(int64_t nsets, int64_t nchunks, const double* __restrict__ partial,
+                                                     const float* __restrict__ gsum, float* __restrict__ sum,
+                                                     float* __restrict__ g_lam, float* __restrict__ g_alpha,
+                                                     float* __restrict__ g_delta, float* __restrict__ g_mu) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= nsets) return;
+  double acc[kGhQ] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = 0; c < nchunks; ++c)
+#pragma unroll
+    for (int q = 0; q < kGhQ; ++q) acc[q] += partial[(i * nchunks + c) * kGhQ + q];
+  const double g = gsum ? (double)gsum[i] : 1.0;
+  sum[i] = (float)acc[0];
+  if (g_lam) g_lam[i] = (float)(g * acc[1]);
+  if (g_alpha) g_alpha[i] = (float)(g * acc[2]);
+  if (g_delta) g_delta[i] = (float)(g * acc[3]);
+  if (g_mu) g_mu[i] = (float)(g * acc[4]);
+}
+
+}  // namespace bk
+
+using namespace bk;
+
+extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, const float* delta,
+                                  const float* mu, int64_t nsamp, const float* y, const float* grad_sum, float* sum,
+                                  float* g_lam, float* g_alpha, float* g_delta, float* g_mu, int nbins,
+                                  int range_mode, const bessel_mlp* mlp, void* hip_stream) {
+  (void)mlp;
+  if (nsets < 0 || nsamp < 0) return set_error(BESSEL_ERR_ARG, "nsets and nsamp must be >= 0");
+  if (range_mode != BESSEL_RANGE_NEWTON)
+    return set_error(range_mode == BESSEL_RANGE_MLP ? BESSEL_ERR_UNSUPPORTED : BESSEL_ERR_RANGE_MODE,
+                     "the per-set sums use the Newton bracket");
+  if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
+    return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
+  if (nsets == 0) return BESSEL_OK;
+  if (!lam || !alpha || !delta || !mu || !sum || (nsamp > 0 && !y))
+    return set_error(BESSEL_ERR_ARG, "lam, alpha, delta, mu, sum and y must be non-NULL");
+  const size_t sb = (size_t)nsets * sizeof(float);
+  const void* ins[6] = {lam, alpha, delta, mu, grad_sum, y};
+  const size_t inb[6] = {sb, sb, sb, sb, sb, (size_t)nsamp * sizeof(float)};
+  void* outs[5] = {sum, g_lam, g_alpha, g_delta, g_mu};
+  for (int a = 0; a < 5; ++a) {
+    for (int b = 0; b < 6; ++b)
+      if (overlaps(outs[a], sb, ins[b], inb[b])) return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+    for (int b = a + 1; b < 5; ++b)
+      if (overlaps(outs[a], sb, outs[b], sb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
+  }
+  const int64_t nchunks = nsamp > 0 ? (nsamp + kBlock - 1) / kBlock : 1;
+  const int64_t nblocks = nsets * nchunks;
+  if (nblocks > 0x7fffffffLL) return set_error(BESSEL_ERR_ARG, "nsets x nsamp too large for one launch");
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* partial = nullptr;
+  hipError_t e = hipMallocAsync((void**)&partial, (size_t)nblocks * kGhQ * sizeof(double), st);
+  if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
+  const dim3 grid((unsigned)nblocks);
+  switch (nbins) {
+    case 64: k_gh_partial<64><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
+    case 128: k_gh_partial<128><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
+    case 256: k_gh_partial<256><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
+    default: k_gh_partial<0><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
+  }
+  int rc = check_launch("k_gh_partial");
+  if (rc == BESSEL_OK) {
+    k_gh_final<<<dim3((unsigned)((nsets + kBlock - 1) / kBlock)), kBlock, 0, st>>>(nsets, nchunks, partial, grad_sum,
+                                                                               sum, g_lam, g_alpha, g_delta, g_mu);
+    rc = check_launch("k_gh_final");
+  }
+  e = hipFreeAsync(partial, st);
+  if (rc == BESSEL_OK && e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
+  return rc;
+}

@@ -107,3 +107,20 @@ def test_error_status_names():
     assert _lib.STATUS[-3] == "BESSEL_ERR_NBINS"
     with pytest.raises(_lib.BesselError):
         _lib.check(-3, "x")
+
+
+def test_gh_argument_errors(lib):
+    args = [FAKE_A, FAKE_A, FAKE_A, FAKE_A, 4, FAKE_B, NULL, FAKE_C, NULL, NULL, NULL, NULL]
+    assert lib.bessel_gh_logk_sum(4, *args, 128, 1, NULL, NULL) == -7  # learned range: unsupported here
+    assert lib.bessel_gh_logk_sum(4, *args, 1, 0, NULL, NULL) == -3
+    assert lib.bessel_gh_logk_sum(-1, *args, 128, 0, NULL, NULL) == -1
+    assert lib.bessel_gh_logk_sum(0, *args, 128, 0, NULL, NULL) == 0
+    bad = [FAKE_A, FAKE_A, FAKE_A, FAKE_A, 4, FAKE_B, NULL, FAKE_A, NULL, NULL, NULL, NULL]
+    assert lib.bessel_gh_logk_sum(4, *bad, 128, 0, NULL, NULL) == -6
+
+
+def test_mlp_argument_errors(lib):
+    h = ctypes.c_void_p()
+    assert lib.bessel_mlp_create(FAKE_A, 7, ctypes.byref(h)) == -1  # wrong parameter count
+    assert lib.bessel_mlp_create(NULL, 4490, NULL) == -1
+    assert lib.bessel_mlp_destroy(NULL) == 0
