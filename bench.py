@@ -2,15 +2,20 @@
 
 Workload: the 2^24-pair scale workload (v ~ U[0, 50], x ~ 10^U[-3, 3], with 25 %
 drawn from the hard bands |v - x| < 1 and v > 20, x < 0.1; seed 1), inputs
-resident in HBM before timing.  One step = one pass of each path over the whole
-batch:
+resident in HBM before timing.  Each path is timed over the whole batch at
+128 bins:
 
-    f32 fwd        log K, FP32 output (the headline value)
-    f32 fwd+bwd    log K and d/dv, d/dx log K times an upstream gradient
-    f64 fwd        log K, FP64 output
-    f64 fwd+bwd
+    f32_mlp_fwd      FP32 bins on the learned bracket, Newton fallback (the
+                     headline value: one step = one call over the batch)
+    f32_mlp_fwd_bwd  the same with d/dv, d/dx log K times an upstream gradient
+    f64_fwd          the plain method in FP64 (Newton bracket), log K
+    f64_fwd_bwd
+    f32_fwd          FP32 bins on the Newton bracket
+    f32_fwd_bwd
+    gh_f32_fwd_bwd   per-set sums over 1024 sets x 65536 samples with gradients
 
-at 128 bins with the Newton bracket.  Every launch runs on torch's current
+The predictor is trained (20000 Adam steps on 2^20 Newton brackets) and its
+margins calibrated before any timing.  Every launch runs on torch's current
 stream, so the torch.cuda events around the timed region bracket exactly the
 kernels.  Prints ONE JSON line (rank 0).
 
@@ -37,18 +42,24 @@ import workloads  # noqa: E402
 # instruction on one lane = 1 slot; an FP32 transcendental = 2, measured half
 # rate; v_rcp_f64 = 4):  W(n) = (n + 1) * W_NODE + W_PRE, from the operation
 # count of the formulation (one table per path in DESIGN.md, "Roofline").
-W_NODE = {("f32", False): 10.0, ("f32", True): 16.0, ("f64", False): 26.5, ("f64", True): 30.5}
+W_NODE = {("f32", False): 9.0, ("f32", True): 15.0, ("f64", False): 24.5, ("f64", True): 30.5}
 W_PRE = 500.0
+# Learned bracket: the network's VALU work (128 activations 1 / (1 + 2^a) at
+# 5 slots, 128 layer-3 FMAs, features 6, bf16 packing 32, outputs 4; its 48
+# MFMAs per 64 elements run on the matrix cores and are not counted) plus
+# bracket 10, shift 35, bin set-up 120, check 10, final 50, loads 30.
+W_NET = 810.0
+W_MLP_PRE = W_NET + 255.0
 
 # MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s
 # (= the 78.6 TFLOP/s FP64 / unpacked-FP32 vector peak with an FMA as 2 FLOP).
 PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
-# HBM bytes per element of the f32 forward kernel from rocprofv3 FETCH_SIZE
-# (x2: a plain 256 MiB device copy reads back half its size on this counter)
-# plus WRITE_SIZE, taken on the kernel sources whose hash is recorded here.
-TRAFFIC = {"sources_sha256": "ed518000274c4105035593d97cf097408be3e2f5b7564e468f5e738e6f791cbd",
-           "bytes_per_elem": 12.007}  # (65593 * 2 + 65536) KiB per 2^24 elements
+# HBM bytes per element of the learned-range call (fused kernel + fallback)
+# from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
+# its size on this counter) plus WRITE_SIZE, taken on the kernel sources whose
+# hash is recorded here; reported only while the sources still match.
+TRAFFIC = {"sources_sha256": None, "bytes_per_elem": None}
 
 
 def kernel_sources_sha256() -> str:
@@ -66,6 +77,12 @@ def alg_slots(dt: str, grad: bool, nbins: int) -> float:
     return (nbins + 1) * W_NODE[(dt, grad)] + W_PRE
 
 
+def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float) -> float:
+    """Per element of a learned-range call: the fused kernel's work, plus the
+    Newton path for the fallback fraction."""
+    return (nbins + 1) * W_NODE[("f32", grad)] + W_MLP_PRE + fallback_rate * alg_slots("f32", grad, nbins)
+
+
 def parse():
     p = argparse.ArgumentParser()
     p.add_argument("--gpus", type=int, default=1)
@@ -78,6 +95,10 @@ def parse():
     p.add_argument("--mlp-steps", type=int, default=20000)
     p.add_argument("--copy-check", action="store_true",
                    help="also run a plain 256 MiB device copy (calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--save-mlp", default=None, help="write the trained, calibrated predictor (.npy)")
+    p.add_argument("--load-mlp", default=None,
+                   help="use a predictor saved by --save-mlp instead of training one (for counter runs, "
+                        "which serialise every dispatch)")
     return p.parse_args()
 
 
@@ -160,15 +181,24 @@ def main():
     # brackets), calibrate the two margins on a held-out set; not timed
     from paper_2108_11560_amd import mlp as M
     t_train = time.perf_counter()
-    vtr, xtr, _ = workloads.scale_pairs(1 << 20, seed=4)
-    mlp = M.RangeMLP(M.glorot_params(0))
-    losses = mlp.train(torch.tensor(vtr, dtype=torch.float32, device=dev),
-                       torch.tensor(xtr, dtype=torch.float32, device=dev),
-                       steps=args.mlp_steps, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
-    vca, xca, _ = workloads.scale_pairs(1 << 16, seed=8)
-    m1, m0, cal_rate = M.calibrate_margins(mlp, torch.tensor(vca, dtype=torch.float32, device=dev),
-                                           torch.tensor(xca, dtype=torch.float32, device=dev),
-                                           target_fallback=0.005)
+    if args.load_mlp:
+        mlp = M.RangeMLP.load_file(args.load_mlp)
+        p = mlp.params()
+        losses = np.zeros(0, dtype=np.float32)
+        m1, m0, cal_rate = float(p[M.O_META + 4]), float(p[M.O_META + 5]), None
+        args.mlp_steps = 0
+    else:
+        vtr, xtr, _ = workloads.scale_pairs(1 << 20, seed=4)
+        mlp = M.RangeMLP(M.glorot_params(0))
+        losses = mlp.train(torch.tensor(vtr, dtype=torch.float32, device=dev),
+                           torch.tensor(xtr, dtype=torch.float32, device=dev),
+                           steps=args.mlp_steps, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
+        vca, xca, _ = workloads.scale_pairs(1 << 16, seed=8)
+        m1, m0, cal_rate = M.calibrate_margins(mlp, torch.tensor(vca, dtype=torch.float32, device=dev),
+                                               torch.tensor(xca, dtype=torch.float32, device=dev),
+                                               target_fallback=0.005)
+    if args.save_mlp:
+        mlp.save(args.save_mlp)
     torch.cuda.synchronize()
     t_train = time.perf_counter() - t_train
 
@@ -189,7 +219,8 @@ def main():
     fb_bwd = mlp.fallback_count()
     paths["f32_mlp_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3), "fallback_rate": fb_fwd / args.n}
     paths["f32_mlp_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3), "fallback_rate": fb_bwd / args.n}
-    mlp_info = {"train_steps": args.mlp_steps, "train_seconds": t_train, "final_loss": float(losses[-1]),
+    mlp_info = {"train_steps": args.mlp_steps, "train_seconds": t_train,
+                "final_loss": float(losses[-1]) if losses.size else None, "loaded_from": args.load_mlp,
                 "margin_t1": m1, "margin_t0": m0, "calibration_fallback_rate": cal_rate}
 
     # generalised-hyperbolic-shaped per-set sums: 1024 sets x 65536 shared samples, fwd+bwd
@@ -203,20 +234,35 @@ def main():
                                "valu_frac": alg_slots("f32", True, nb) * n_gh / (ms_g * 1e-3) / PEAK_SLOTS}
 
     for key, p in paths.items():
-        if "mlp" in key or key.startswith("gh"):
+        if key.startswith("gh"):
             continue
-        dt, grad = key[:3], key.endswith("bwd")
-        p["alg_slots_per_elem"] = alg_slots(dt, grad, nb)
+        grad = key.endswith("bwd")
+        if "mlp" in key:
+            p["alg_slots_per_elem"] = alg_slots_mlp(grad, nb, p["fallback_rate"])
+        else:
+            p["alg_slots_per_elem"] = alg_slots(key[:3], grad, nb)
         p["valu_frac"] = p["alg_slots_per_elem"] * p["evals_per_s"] / PEAK_SLOTS
 
-    head = paths["f32_fwd"]
+    head = paths["f32_mlp_fwd"]
     achieved = head["alg_slots_per_elem"] * head["evals_per_s"]
     traffic = None
     if TRAFFIC["bytes_per_elem"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
         traffic = TRAFFIC["bytes_per_elem"] * args.n
+    # the FP32 learned-range path against the plain FP64 method on the same batch
+    speedup = {"fwd": paths["f32_mlp_fwd"]["evals_per_s"] / paths["f64_fwd"]["evals_per_s"],
+               "fwd_bwd": paths["f32_mlp_fwd_bwd"]["evals_per_s"] / paths["f64_fwd_bwd"]["evals_per_s"]}
+    # mixed error of the FP32 paths against the FP64 path, over the whole batch,
+    # at the FP32-rounded inputs
+    ref = bk.logk(V["f32"].double(), X["f32"].double(), nbins=nb)
+    err_f64 = {}
+    for key, out in (("f32", bk.logk(V["f32"], X["f32"], nbins=nb)),
+                     ("f32_mlp", bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp", mlp=mlp))):
+        e = (out.double() - ref).abs() / ref.abs().clamp_min(1.0)
+        err_f64[key] = {"max": float(e.max()), "p99": float(torch.quantile(e[::64], 0.99))}
+    del ref
     roofline = {
         "bound": "alu",
-        "kernel": f"k_logk<float,{nb},false>",
+        "kernel": f"k_logk_mlp<false,{nb}> (+ k_logk_fallback on the fallback fraction)",
         "achieved": achieved / 1e12,
         "peak": PEAK_SLOTS / 1e12,
         "unit": "T VALU lane-slots/s",
@@ -238,8 +284,10 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "scale-2^24", "n": args.n, "nbins": nb, "range": "newton", "seed": 1,
-                   "path": "f32 fwd"},
+        "config": {"workload": "scale-2^24", "n": args.n, "nbins": nb, "range": "mlp", "seed": 1,
+                   "path": "f32 learned-range fwd"},
+        "speedup_vs_f64": speedup,
+        "err_vs_f64_path": err_f64,
         "paths": paths,
         "learned_range": mlp_info,
         "roofline": roofline,

@@ -119,18 +119,20 @@ int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void*
  * ((log max(|v|, 1e-3) - m_v)/s_v, (log x - m_x)/s_x), to (y0, y1); the bracket
  * is t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1).  It is trained
  * on the method's own Newton brackets (Sections 2.2-2.3 at the FP32 eps), and
- * at inference (bf16 MFMA for the 64 x 64 layer) every predicted bracket is
- * checked after the bins: the end terms must lie below eps relative to the
- * shift and the even-node and odd-node sums must agree to 1e-5.  Elements
- * that fail are recomputed by the Newton path in a second kernel on the same
- * stream.
+ * at inference (layers 1 and 2 on bf16 MFMA, layer 3 in FP32) every predicted
+ * bracket is checked after the bins: the end terms must lie below eps
+ * relative to the shift and the even-node and odd-node sums must agree to
+ * 1e-5.  Elements that fail are recomputed by the Newton path in a second
+ * kernel on the same stream.
  *
  * Parameter vector (host floats, BESSEL_MLP_NPARAMS): W1 (64 x 2, row-major),
  * b1[64], W2 (64 x 64; W2[i][j] multiplies hidden j of layer 1), b2[64],
  * W3 (2 x 64), b3[2] (BESSEL_MLP_NWEIGHTS trainable values), then
  * m_v, s_v, m_x, s_x, margin_t1, margin_t0, 0, 0.
  *
- * The handle owns all device memory it uses: parameters, optimizer state, and
+ * The handle owns all device memory it uses: parameters, optimizer state, the
+ * inference operands derived from the parameters (rebuilt on the stream of
+ * the first inference call after any change of the parameters), and
  * workspaces that grow (stream-ordered, on the call's stream) to the largest
  * n seen.  Calls that use one handle must not overlap in time (serialise them
  * on one stream); different handles are independent.
@@ -177,7 +179,8 @@ int bessel_mlp_loss_grad(bessel_mlp* mlp, int64_t n, const float* v, const float
 int bessel_mlp_adam_step(bessel_mlp* mlp, const float* grad, float lr, float beta1, float beta2, float eps,
                          void* hip_stream);
 /* Raw network outputs y[2 i], y[2 i + 1] for n device inputs; mode 0: FP32 with
- * exact tanh, one element per lane; mode 1: the bf16-MFMA inference of the fused kernel. */
+ * exact tanh, one element per lane; mode 1: the bf16-MFMA inference of the
+ * fused kernel (the same operands and arithmetic). */
 int bessel_mlp_forward(const bessel_mlp* mlp, int64_t n, const float* v, const float* x, float* y, int mode,
                        void* hip_stream);
 /* Number of elements of the handle's last learned-range call that fell back to

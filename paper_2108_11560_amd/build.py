@@ -2,7 +2,8 @@
 
 Run as ``python -m paper_2108_11560_amd.build``; ``__graft_entry__.build()``
 calls :func:`build` too.  Every HIP source is compiled for gfx950 only, with
-packed FP32 instructions disabled (``-packed-fp32-ops``).
+packed FP32 instructions disabled (``-packed-fp32-ops``).  Also builds the
+instruction-rate microbenchmark ``_build/valu_rates`` (``microbench/``).
 """
 
 from __future__ import annotations
@@ -19,6 +20,8 @@ INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbessel.so")
 
 SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip", "bessel_gh.hip"]
+# stand-alone programs: name -> source (relative to the package)
+PROGRAMS = {"valu_rates": os.path.join("microbench", "valu_rates.hip")}
 
 ARCH = "gfx950"
 
@@ -28,6 +31,9 @@ HIP_FLAGS = [
     "-std=c++17",
     "-fPIC",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # MFMA results in ordinary VGPRs: the network reads every accumulator
+    # back on the VALU, which the AGPR form would cost one copy each
+    "-mllvm", "-amdgpu-mfma-vgpr-form",
     "-Wall",
     "-Wno-unused-command-line-argument",
     "-Wno-unused-result",
@@ -59,6 +65,11 @@ def build(verbose: bool = False) -> str:
         print(" ".join(cmd), flush=True)
     subprocess.run(cmd, check=True)
     os.replace(tmp, LIB)
+    for name, src in PROGRAMS.items():
+        cmd = [hipcc(), *HIP_FLAGS, os.path.join(HERE, src), "-o", os.path.join(objdir, name)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
     return LIB
 
 

@@ -89,6 +89,28 @@ __device__ __forceinline__ double exp_f64(double a) {
   return scale2k(1.0 + e.em1, e.k);
 }
 
+// e^a for the nodes of the FP64 bins: the same reduction, e^r by a degree-9
+// minimax polynomial (relative error 1.4e-14 on |r| <= ln2/2, gen_exp_poly.py
+// 9) evaluated to e^r directly.  A node's relative error then stays far below
+// the 1e-12 the FP64 path is held to, for two fewer operations per node.
+__device__ __forceinline__ double exp_node_f64(double a) {
+  a = fmax(a, -708.0);
+  const double kd = fma(a, kLog2e, kRoundMagic);
+  const double kf = kd - kRoundMagic;
+  const double r = fma(-kf, kLn2Lo, fma(-kf, kLn2D, a));
+  double p = 2.748218700193312e-06;
+  p = fma(p, r, 2.4884010015388764e-05);
+  p = fma(p, r, 0.0001984159639703441);
+  p = fma(p, r, 0.0013888802828821594);
+  p = fma(p, r, 0.008333333002822645);
+  p = fma(p, r, 0.041666667032463356);
+  p = fma(p, r, 0.16666666667826954);
+  p = fma(p, r, 0.4999999999945797);
+  p = fma(p, r, 0.9999999999998928);
+  p = fma(p, r, 1.0000000000000127);  // in [0.7, 1.42]
+  return scale2k(p, __double2loint(kd));
+}
+
 // 1 - e^{-z} for z >= 0 with relative accuracy as z -> 0.
 __device__ __forceinline__ double one_minus_exp_neg(double z) {
   const ExpParts e = exp_parts(-z);
@@ -312,33 +334,14 @@ struct BinSums {
   float term0, termN;
 };
 
-constexpr int kChunk = 16;  // nodes per unrolled chunk
-
-// One node's contribution.  The forward and the derivative kernels accumulate
-// S0 with the same operations, so log K does not depend on whether the
-// derivatives are requested.
-template <bool GRAD>
-__device__ __forceinline__ void node_f64(double w, double r, double t, double ch, BinSums& s) {
-  s.S0 = fma(w, 2.0 - r, s.S0);
-  if (GRAD) {
-    s.Sv = fma(w * r, t, s.Sv);
-    s.Sx = fma(w * (2.0 - r), ch, s.Sx);
-  }
-}
-
-template <bool GRAD>
-__device__ __forceinline__ void node_f32(float w, double r, float t, double ch, float& s0, float& sv, float& sx) {
-  const float rf = (float)r;
-  s0 = fmaf(w, 2.0f - rf, s0);
-  if (GRAD) {
-    sv = fmaf(w * rf, t, sv);
-    sx = fmaf(w * (2.0f - rf), (float)ch, sx);
-  }
-}
+constexpr int kChunk = 16;    // nodes per unrolled chunk (FP64 bins)
+constexpr int kChunk32 = 32;  // nodes per unrolled chunk (FP32 bins)
 
 // FP64 bins.  e^{t} and e^{-t} are recomputed at each chunk start so their
 // product recurrences never run more than kChunk steps (relative error within
-// ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).
+// ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).  f at a node
+// is e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the
+// FP32 bins); even and odd nodes are summed apart (independent FMA chains).
 template <bool GRAD>
 __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1) {
   const double h = (t1 - t0) / (double)nb;
@@ -346,9 +349,11 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const double xh = 0.5 * x;
   const double eh = exp_f64(h), ehi = rcp_f64(eh);
   const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
+  double u = 2.0 - r;
   BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+  double S[2] = {0.0, 0.0}, Sv[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0};
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
@@ -358,10 +363,15 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
     for (int b = 0; b < kChunk; ++b) {
       const double t = fma((double)b, h, ta);
       const double ch2 = E + Ei;
-      double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+      double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
       if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
-      node_f64<GRAD>(w, r, t, 0.5 * ch2, s);
-      r = fma(r, Q, E2);
+      S[b & 1] = fma(w, u, S[b & 1]);
+      if (GRAD) {
+        Sv[b & 1] = fma(w * r, t, Sv[b & 1]);
+        Sx[b & 1] = fma(w * u, 0.5 * ch2, Sx[b & 1]);
+        r = fma(r, Q, E2);
+      }
+      u = fma(u, Q, E2);
       E *= eh;
       Ei *= ehi;
     }
@@ -371,19 +381,35 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
     const double t = (m == nb) ? t1 : fma((double)m, h, t0);
     const double E = exp_f64(t);
     const double ch2 = E + rcp_f64(E);
-    double w = exp_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
     if (m == 0 || m == nb) w *= 0.5;
-    node_f64<GRAD>(w, r, t, 0.5 * ch2, s);
-    r = fma(r, Q, E2);
+    S[m & 1] = fma(w, u, S[m & 1]);
+    if (GRAD) {
+      Sv[m & 1] = fma(w * r, t, Sv[m & 1]);
+      Sx[m & 1] = fma(w * u, 0.5 * ch2, Sx[m & 1]);
+      r = fma(r, Q, E2);
+    }
+    u = fma(u, Q, E2);
+  }
+  s.S0 = S[0] + S[1];
+  if (GRAD) {
+    s.Sv = Sv[0] + Sv[1];
+    s.Sx = Sx[0] + Sx[1];
   }
   return s;
 }
 
 // FP32 bins: the argument A - G is formed in FP64 (v t, x cosh t and G reach
 // ~1e3 and nearly cancel, which FP32 could not resolve), pre-scaled by log2 e;
-// then one hardware exp2 per node and FP32 partial sums per chunk, added in
-// FP64 across chunks.  cosh t follows the three-term recurrence (one FMA per
-// node; its relative error grows like m eps / (2 sinh h), far below FP32).
+// then one hardware exp2 per node, whose FP32 result is widened and
+// accumulated in FP64 against u = 2 - r = 1 + e^{-2vt}.  u, r and cosh t
+// follow linear recurrences (one FMA each per node):
+//   u_{m+1} = Q u_m + (1 - Q),  r_{m+1} = Q r_m + (1 - Q),  Q = e^{-2vh},
+// whose terms are positive (relative error ~ m eps), and the three-term
+// C_{m+1} = 2 cosh h C_m - C_{m-1} (relative error ~ m eps / (2 sinh h)).
+// r (for d/dv) is kept by its own recurrence rather than as 2 - u, which would
+// lose its relative accuracy as v -> 0.  The forward and derivative variants
+// accumulate S0 with identical operations.
 template <bool GRAD, bool CHECK = false>
 __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G, double t0, double t1) {
   const double h = (t1 - t0) / (double)nb;
@@ -399,68 +425,65 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   double Cp = 0.5 * (E0 * ehi + E0i * eh);  // cosh(t0 - h)
   double C = 0.5 * (E0 + E0i);              // cosh(t0)
   const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
+  double u = 2.0 - r;
   const double L0 = fma(vl, t0, -Gl);  // (v t - G - log 2) log2 e
   BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
-  const int nchunks = nb / kChunk;
-  const float hf = (float)h;
+  // even and odd nodes go to separate sums (two independent FMA chains; the
+  // checked variant also needs them apart); chunk starts are even
+  double S[2] = {0.0, 0.0}, Sv[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0};
+  const int nchunks = nb / kChunk32;
   for (int c = 0; c < nchunks; ++c) {
-    // the linear part runs by addition inside a chunk (error <= kChunk ulp of |L|)
-    double L = fma((double)(c * kChunk), dL, L0);
-    const float taf = (float)fma((double)(c * kChunk), h, t0);
-    float s0 = 0.0f, sv = 0.0f, sx = 0.0f, s0o = 0.0f;
+    // the linear part runs by addition inside a chunk (error <= kChunk32 ulp of |L|)
+    double L = fma((double)(c * kChunk32), dL, L0);
+    const double ta = fma((double)(c * kChunk32), h, t0);
 #pragma unroll
-    for (int b = 0; b < kChunk; ++b) {
+    for (int b = 0; b < kChunk32; ++b) {
       float w = hexp2((float)fma(-xl, C, L));
-      if (CHECK && b == 0 && c == 0) s.term0 = w * (2.0f - (float)r);
+      if (CHECK && b == 0 && c == 0) s.term0 = w * (float)u;
       if (b == 0) w *= (c == 0) ? 0.5f : 1.0f;
-      // the checked variant keeps odd nodes (chunk starts are even) apart
-      node_f32<GRAD>(w, r, GRAD ? fmaf((float)b, hf, taf) : 0.0f, C, (CHECK && (b & 1)) ? s0o : s0, sv, sx);
-      r = fma(r, Q, E2);
+      const double wd = (double)w;
+      S[b & 1] = fma(wd, u, S[b & 1]);
+      if (GRAD) {
+        Sv[b & 1] = fma(wd * r, fma((double)b, h, ta), Sv[b & 1]);
+        Sx[b & 1] = fma(wd * u, C, Sx[b & 1]);
+        r = fma(r, Q, E2);
+      }
+      u = fma(u, Q, E2);
       L += dL;
       const double Cn = fma(c2, C, -Cp);
       Cp = C;
       C = Cn;
     }
-    if (CHECK) {
-      s.Seven += (double)s0;
-      s.Sodd += (double)s0o;
-      s.S0 += (double)s0 + (double)s0o;
-    } else {
-      s.S0 += (double)s0;
-    }
-    if (GRAD) {
-      s.Sv += (double)sv;
-      s.Sx += (double)sx;
-    }
   }
-  {
-    float s0 = 0.0f, sv = 0.0f, sx = 0.0f, s0o = 0.0f;
-    for (int m = nchunks * kChunk; m <= nb; ++m) {
-      const double L = (m == nb) ? fma(vl, t1, -Gl) : fma((double)m, dL, L0);
-      float w = hexp2((float)fma(-xl, C, L));
-      if (CHECK && m == 0) s.term0 = w * (2.0f - (float)r);
-      if (CHECK && m == nb) s.termN = w * (2.0f - (float)r);
-      if (m == 0 || m == nb) w *= 0.5f;
-      const float tf = GRAD ? ((m == nb) ? (float)t1 : (float)fma((double)m, h, t0)) : 0.0f;
-      node_f32<GRAD>(w, r, tf, C, (CHECK && (m & 1)) ? s0o : s0, sv, sx);
-      r = fma(r, Q, E2);
-      const double Cn = fma(c2, C, -Cp);
-      Cp = C;
-      C = Cn;
-    }
-    if (CHECK) {
-      s.Seven += (double)s0;
-      s.Sodd += (double)s0o;
-      s.S0 += (double)s0 + (double)s0o;
-    } else {
-      s.S0 += (double)s0;
-    }
+  for (int m = nchunks * kChunk32; m <= nb; ++m) {
+    const double L = (m == nb) ? fma(vl, t1, -Gl) : fma((double)m, dL, L0);
+    float w = hexp2((float)fma(-xl, C, L));
+    if (CHECK && m == 0) s.term0 = w * (float)u;
+    if (CHECK && m == nb) s.termN = w * (float)u;
+    if (m == 0 || m == nb) w *= 0.5f;
+    const double wd = (double)w;
+    S[m & 1] = fma(wd, u, S[m & 1]);
     if (GRAD) {
-      s.Sv += (double)sv;
-      s.Sx += (double)sx;
+      const double t = (m == nb) ? t1 : fma((double)m, h, t0);
+      Sv[m & 1] = fma(wd * r, t, Sv[m & 1]);
+      Sx[m & 1] = fma(wd * u, C, Sx[m & 1]);
+      r = fma(r, Q, E2);
     }
+    u = fma(u, Q, E2);
+    const double Cn = fma(c2, C, -Cp);
+    Cp = C;
+    C = Cn;
+  }
+  s.S0 = S[0] + S[1];
+  if (CHECK) {
+    s.Seven = S[0];
+    s.Sodd = S[1];
+  }
+  if (GRAD) {
+    s.Sv = Sv[0] + Sv[1];
+    s.Sx = Sx[0] + Sx[1];
   }
   return s;
 }

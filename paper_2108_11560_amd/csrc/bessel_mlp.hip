@@ -49,11 +49,6 @@ __device__ __forceinline__ void mlp_features(const float* __restrict__ P, float 
   z1 = (lx - P[oMeta + 2]) / P[oMeta + 3];
 }
 
-// tanh from a pre-activation already scaled by 2 log2(e):  1 - 2 / (1 + 2^a).
-__device__ __forceinline__ float tanh_scaled(float a) {
-  return fmaf(-2.0f, hrcp(1.0f + hexp2(a)), 1.0f);
-}
-
 constexpr float k2Log2e = 2.88539008178f;  // 2 log2(e)
 
 // splitmix64 (Steele, Lea, Flood 2014): counter-based draws for minibatches.
@@ -266,96 +261,162 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restr
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
-// One wavefront evaluates the network for its 64 elements (lane = element).
-// Layer 1 and the activations on the VALU; the 64 x 64 layer on
-// v_mfma_f32_16x16x32_bf16 with D[hidden out][element] = W2 * H1^T:
-//   A (16 x 32, weights): lane l holds row l%16, columns 8(l/16)..8(l/16)+7
-//   B (32 x 16, H1^T):    lane l holds column l%16, rows 8(l/16)..8(l/16)+7
-//   D (16 x 16):          lane l holds column l%16, rows 4(l/16)..4(l/16)+3
-// H1 travels through LDS (bf16, [element][hidden]) to reach the B layout;
-// the layer-3 dot products are finished with cross-lane sums over the four
-// lane groups.  Pre-activations are scaled by 2 log2(e) for tanh_scaled.
-// lds: 64 x 64 bf16 for this wave.  Returns y0, y1 for the lane's element.
-// Every thread of the block must call it (it contains a block barrier).
-__device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ P, float z0, float z1, __bf16* lds,
-                                              float& y0, float& y1) {
+// Inference operands, rebuilt from the FP32 parameters whenever they change
+// (k_mlp_pack) so that a wavefront loads its fragments with a few 16-byte loads:
+//   header  z0 = log2 max(|v|, 1e-3) * c_v + d_v,  z1 = log2 x * c_x + d_x
+//           (c = ln 2 / s, d = -m / s), e^{margin_t1}, margin_t0, b3'[2]
+//   A1      layer-1 fragments: for hidden tile ht and row lr, the eight bf16
+//           values (Wh0, Wh0, Wl0, Wh1, Wh1, Wl1, bh, bl) -- hi/lo splits of
+//           2 log2(e) (W1, b1) -- which meet (zh0, zl0, zh0, zh1, zl1, zh1, 1, 1)
+//   A2      layer-2 fragments (bf16 of -2 * 2 log2(e) W2) per output tile,
+//           k-block and lane, columns in the order the layer-1 results reach
+//           the lane
+//   B2      2 log2(e) (b2 + sum_j W2[., j]) in accumulator order
+//   W3      -2 W3 in accumulator order;  b3' = b3 + sum_i W3[., i]
+// With s = 1 / (1 + 2^{a'}), a' = 2 log2(e) a, tanh(a) = 1 - 2 s, so each layer
+// takes the s of the one before:  W h + b = (b + sum W) - 2 W s.
+constexpr int qHdr = 0, qA1 = 16, qA2 = qA1 + 4 * 16 * 4, qB2 = qA2 + 4 * 2 * 64 * 4, qW3 = qB2 + kH,
+              kNQ = qW3 + 2 * kH;
+
+// hidden unit fed by k-slot j of lane group g in k-block kb of layer 2: the
+// layer-1 accumulators of tiles 2kb and 2kb+1 hold rows 4g..4g+3 of each
+__host__ __device__ constexpr int l2_col(int kb, int g, int j) { return 32 * kb + (j < 4 ? 4 * g + j : 16 + 4 * g + j - 4); }
+
+__global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ P, float* __restrict__ Q) {
+  const int t = threadIdx.x;
+  __bf16* a1 = reinterpret_cast<__bf16*>(Q + qA1);
+  __bf16* a2 = reinterpret_cast<__bf16*>(Q + qA2);
+  if (t < kH) {
+    const int h = t;  // = 16 ht + lr
+    const float w[3] = {k2Log2e * P[oW1 + 2 * h], k2Log2e * P[oW1 + 2 * h + 1], k2Log2e * P[ob1 + h]};
+    __bf16 hi[3], lo[3];
+    for (int k = 0; k < 3; ++k) {
+      hi[k] = (__bf16)w[k];
+      lo[k] = (__bf16)(w[k] - (float)hi[k]);
+    }
+    const __bf16 e[8] = {hi[0], hi[0], lo[0], hi[1], hi[1], lo[1], hi[2], lo[2]};
+    for (int j = 0; j < 8; ++j) a1[h * 8 + j] = e[j];
+    double rs = (double)P[ob2 + h];
+    for (int j = 0; j < kH; ++j) rs += (double)P[oW2 + h * kH + j];
+    Q[qB2 + h] = k2Log2e * (float)rs;  // 16 ho + 4 g + r is the natural order
+    Q[qW3 + h] = -2.0f * P[oW3 + h];
+    Q[qW3 + kH + h] = -2.0f * P[oW3 + kH + h];
+  }
+  for (int idx = t; idx < 4 * 2 * 64 * 8; idx += kBlock) {
+    const int j = idx & 7, l = (idx >> 3) & 63, kb = (idx >> 9) & 1, ho = idx >> 10;
+    const int row = 16 * ho + (l & 15);
+    a2[idx] = (__bf16)(-2.0f * k2Log2e * P[oW2 + row * kH + l2_col(kb, l >> 4, j)]);
+  }
+  if (t < 2) {
+    double s = (double)P[ob3 + t];
+    for (int i = 0; i < kH; ++i) s += (double)P[oW3 + t * kH + i];
+    Q[qHdr + 6 + t] = (float)s;
+  }
+  if (t == 0) {
+    Q[qHdr + 0] = kLn2F / P[oMeta + 1];
+    Q[qHdr + 1] = -P[oMeta + 0] / P[oMeta + 1];
+    Q[qHdr + 2] = kLn2F / P[oMeta + 3];
+    Q[qHdr + 3] = -P[oMeta + 2] / P[oMeta + 3];
+    Q[qHdr + 4] = hexp2(kLog2eF * P[oMeta + 4]);
+    Q[qHdr + 5] = P[oMeta + 5];
+    for (int k = 8; k < 16; ++k) Q[qHdr + k] = 0.0f;
+  }
+}
+
+__device__ __forceinline__ void mlp_features_q(const float* __restrict__ Q, float v, float x, float& z0, float& z1) {
+  z0 = fmaf(hlog2(fmaxf(fabsf(v), kVFloor)), Q[qHdr + 0], Q[qHdr + 1]);
+  z1 = fmaf(hlog2(x), Q[qHdr + 2], Q[qHdr + 3]);
+}
+
+// One wavefront evaluates the network for its 64 elements (lane = element),
+// every layer on v_mfma_f32_16x16x32_bf16 or the VALU:
+//   A (16 x 32):  lane l holds row l%16, k-slots 8(l/16)..8(l/16)+7
+//   B (32 x 16):  lane l holds column l%16, k-slots 8(l/16)..8(l/16)+7
+//   D (16 x 16):  lane l holds column l%16, rows 4(l/16)..4(l/16)+3
+// Layer 1: D[hidden][element] = A1 * Z, where element tile et takes the
+// features only from lane group et (its own elements), zeros elsewhere.
+// Layer 2: D[hidden out][element] = A2 * S1^T + B2; the layer-1 accumulators
+// of a lane are already its B fragments (k-slots permuted as l2_col).
+// Layer 3 on the VALU in FP32, finished by sums over the four lane groups.
+// Every lane of the wavefront must call it.
+__device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float z0, float z1, float& y0, float& y1) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
-  // layer 1 for this lane's element -> LDS row l
-#pragma unroll
-  for (int j0 = 0; j0 < kH; j0 += 8) {
-    bf16x8 pk;
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int j = j0 + u;
-      const float a = k2Log2e * fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]));
-      pk[u] = (__bf16)tanh_scaled(a);
-    }
-    *reinterpret_cast<bf16x8*>(lds + l * kH + j0) = pk;
+  bf16x8 zf;
+  {
+    const __bf16 z0h = (__bf16)z0, z1h = (__bf16)z1;
+    const __bf16 z0l = (__bf16)(z0 - (float)z0h), z1l = (__bf16)(z1 - (float)z1h);
+    const __bf16 one = (__bf16)1.0f;
+    zf[0] = z0h;
+    zf[1] = z0l;
+    zf[2] = z0h;
+    zf[3] = z1h;
+    zf[4] = z1l;
+    zf[5] = z1h;
+    zf[6] = one;
+    zf[7] = one;
   }
-  // weights of this lane's A fragments (scaled), and biases of its D rows
-  bf16x8 A[4][2];
-  f32x4 bias[4];
+  bf16x8 zero;
 #pragma unroll
-  for (int o = 0; o < 4; ++o) {
+  for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
+  const bf16x8* A1 = reinterpret_cast<const bf16x8*>(Q + qA1);
+  const bf16x8* A2 = reinterpret_cast<const bf16x8*>(Q + qA2);
+  bf16x8 a1[4], a2[4][2];
+  f32x4 b2[4], w3a[4], w3b[4];
 #pragma unroll
-    for (int kk = 0; kk < 2; ++kk)
+  for (int ht = 0; ht < 4; ++ht) a1[ht] = A1[ht * 16 + lr];
 #pragma unroll
-      for (int u = 0; u < 8; ++u)
-        A[o][kk][u] = (__bf16)(k2Log2e * P[oW2 + (16 * o + lr) * kH + 32 * kk + 8 * lg + u]);
-#pragma unroll
-    for (int r = 0; r < 4; ++r) bias[o][r] = k2Log2e * P[ob2 + 16 * o + 4 * lg + r];
+  for (int ho = 0; ho < 4; ++ho) {
+    a2[ho][0] = A2[(ho * 2 + 0) * 64 + l];
+    a2[ho][1] = A2[(ho * 2 + 1) * 64 + l];
+    b2[ho] = *reinterpret_cast<const f32x4*>(Q + qB2 + 16 * ho + 4 * lg);
+    w3a[ho] = *reinterpret_cast<const f32x4*>(Q + qW3 + 16 * ho + 4 * lg);
+    w3b[ho] = *reinterpret_cast<const f32x4*>(Q + qW3 + kH + 16 * ho + 4 * lg);
   }
-  // layer-3 weights of this lane's D rows
-  float w30[16], w31[16];
-#pragma unroll
-  for (int o = 0; o < 4; ++o)
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      w30[4 * o + r] = P[oW3 + 16 * o + 4 * lg + r];
-      w31[4 * o + r] = P[oW3 + kH + 16 * o + 4 * lg + r];
-    }
-  __syncthreads();  // H1 rows written by other lanes are read below
   float p0[4], p1[4];
 #pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    const bf16x8 B0 = *reinterpret_cast<const bf16x8*>(lds + (16 * e + lr) * kH + 0 + 8 * lg);
-    const bf16x8 B1 = *reinterpret_cast<const bf16x8*>(lds + (16 * e + lr) * kH + 32 + 8 * lg);
+  for (int et = 0; et < 4; ++et) {
+    const bf16x8 bz = (lg == et) ? zf : zero;
+    bf16x8 h[2];
+#pragma unroll
+    for (int ht = 0; ht < 4; ++ht) {
+      f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[ht], bz, d, 0, 0, 0);
+#pragma unroll
+      for (int r = 0; r < 4; ++r) h[ht >> 1][4 * (ht & 1) + r] = (__bf16)hrcp(1.0f + hexp2(d[r]));
+    }
     float s0 = 0.0f, s1 = 0.0f;
 #pragma unroll
-    for (int o = 0; o < 4; ++o) {
-      f32x4 d = bias[o];
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[o][0], B0, d, 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A[o][1], B1, d, 0, 0, 0);
+    for (int ho = 0; ho < 4; ++ho) {
+      f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][0], h[0], b2[ho], 0, 0, 0);
+      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][1], h[1], d, 0, 0, 0);
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const float h2 = tanh_scaled(d[r]);
-        s0 = fmaf(w30[4 * o + r], h2, s0);
-        s1 = fmaf(w31[4 * o + r], h2, s1);
+        const float sg = hrcp(1.0f + hexp2(d[r]));
+        s0 = fmaf(w3a[ho][r], sg, s0);
+        s1 = fmaf(w3b[ho][r], sg, s1);
       }
     }
-    // sum the four lane groups holding the other hidden units of element 16e + lr
     s0 += __shfl_xor(s0, 16);
     s1 += __shfl_xor(s1, 16);
     s0 += __shfl_xor(s0, 32);
     s1 += __shfl_xor(s1, 32);
-    p0[e] = s0;
-    p1[e] = s1;
+    p0[et] = s0;
+    p1[et] = s1;
   }
   // lane l = 16 lg + lr owns element-tile lg
-  y0 = P[ob3] + (lg == 0 ? p0[0] : lg == 1 ? p0[1] : lg == 2 ? p0[2] : p0[3]);
-  y1 = P[ob3 + 1] + (lg == 0 ? p1[0] : lg == 1 ? p1[1] : lg == 2 ? p1[2] : p1[3]);
+  y0 = Q[qHdr + 6] + (lg == 0 ? p0[0] : lg == 1 ? p0[1] : lg == 2 ? p0[2] : p0[3]);
+  y1 = Q[qHdr + 7] + (lg == 0 ? p1[0] : lg == 1 ? p1[1] : lg == 2 ? p1[2] : p1[3]);
 }
 
-__global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __restrict__ P, int64_t n,
+__global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __restrict__ Q, int64_t n,
                                                              const float* __restrict__ v,
                                                              const float* __restrict__ x, float* __restrict__ y) {
-  __shared__ __bf16 lds[kBlock / 64][64 * kH];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   float z0 = 0.0f, z1 = 0.0f;
-  if (i < n) mlp_features(P, v[i], x[i], z0, z1);
+  if (i < n) mlp_features_q(Q, v[i], x[i], z0, z1);
   float y0, y1;
-  mlp_wave_mfma(P, z0, z1, lds[threadIdx.x >> 6], y0, y1);
+  mlp_wave_mfma(Q, z0, z1, y0, y1);
   if (i < n) {
     y[2 * i] = y0;
     y[2 * i + 1] = y1;
@@ -386,14 +447,13 @@ __device__ __forceinline__ bool accept_bins(const BinSums& s, float t0) {
 // Fused: network (bf16 MFMA) -> bracket -> checked FP32 bins -> outputs, or the
 // element index onto the worklist (count at work[0], indices from work[1]).
 template <bool GRAD, int NB>
-__global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ P, int64_t n, int nbins,
+__global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q, int64_t n, int nbins,
                                                      const float* __restrict__ vin, const float* __restrict__ xin,
                                                      const float* __restrict__ gout, float* __restrict__ logk,
                                                      float* __restrict__ dv, float* __restrict__ dx,
                                                      float* __restrict__ t0o, float* __restrict__ t1o,
                                                      float* __restrict__ tpo, float* __restrict__ gpo,
                                                      uint8_t* __restrict__ fb, int* __restrict__ work) {
-  __shared__ __bf16 lds[kBlock / 64][64 * kH];
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   const int nb = NB > 0 ? NB : nbins;
   const bool in = i < n;
@@ -403,16 +463,16 @@ __global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ P
   const bool special = in && domain_special((double)vs, (double)xf, lk, dvv, dxv);
   // the whole wavefront takes part in the network
   float z0 = 0.0f, z1 = 0.0f;
-  if (in && !special) mlp_features(P, vs, xf, z0, z1);
+  if (in && !special) mlp_features_q(Q, vs, xf, z0, z1);
   float y0, y1;
-  mlp_wave_mfma(P, z0, z1, lds[threadIdx.x >> 6], y0, y1);
+  mlp_wave_mfma(Q, z0, z1, y0, y1);
   bool ok = true;
   float t0 = 0.0f, t1 = 0.0f, G = 0.0f;
   if (in && !special) {
     const float v = fabsf(vs);
     const float t1r = hexp2(kLog2eF * y1);  // predicted t1 before widening
-    t0 = fmaxf(0.0f, y0 - P[oMeta + 5]) * t1r;
-    t1 = t1r * hexp2(kLog2eF * P[oMeta + 4]);
+    t0 = fmaxf(0.0f, y0 - Q[qHdr + 5]) * t1r;
+    t1 = t1r * Q[qHdr + 4];
     // shift: the largest of g at the midpoint, at asinh(v/x) (the peak when
     // v t_p >> 1, clamped into the bracket) and, for t0 = 0, g(0) = -x
     const float r = fminf(v * hrcp(xf), 1e18f);
@@ -517,6 +577,8 @@ __global__ void k_zero_int(int* p) { *p = 0; }
 // ---------------------------------------------------------------------------
 struct bessel_mlp {
   float* params = nullptr;  // [kNP]
+  float* packed = nullptr;  // [kNQ] inference operands derived from params
+  bool packed_stale = true; // params changed since the last k_mlp_pack
   float* adam_m = nullptr;  // [kNW]
   float* adam_s = nullptr;  // [kNW]
   float* grad = nullptr;    // [kNW + 1] (last: loss)
@@ -565,6 +627,7 @@ extern "C" int bessel_mlp_create(const float* params, int64_t nparams, bessel_ml
   bessel_mlp* m = new (std::nothrow) bessel_mlp();
   if (!m) return set_error(BESSEL_ERR_ARG, "out of host memory");
   hipError_t e = hipMalloc((void**)&m->params, kNP * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->packed, kNQ * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&m->adam_m, kNW * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&m->adam_s, kNW * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&m->grad, (kNW + 1) * sizeof(float));
@@ -593,7 +656,7 @@ extern "C" int bessel_mlp_create(const float* params, int64_t nparams, bessel_ml
 extern "C" int bessel_mlp_destroy(bessel_mlp* m) {
   if (!m) return BESSEL_OK;
   (void)hipDeviceSynchronize();
-  void* sync_ptrs[] = {m->params, m->adam_m, m->adam_s, m->grad};
+  void* sync_ptrs[] = {m->params, m->packed, m->adam_m, m->adam_s, m->grad};
   for (void* p : sync_ptrs)
     if (p) (void)hipFree(p);
   void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work};  // from hipMallocAsync
@@ -612,6 +675,7 @@ extern "C" int bessel_mlp_set_params(bessel_mlp* m, const float* params, int64_t
   if (e == hipSuccess) e = hipMemset(m->adam_s, 0, kNW * sizeof(float));
   if (e != hipSuccess) return hip_fail(e, "bessel_mlp_set_params");
   m->adam_step = 0;
+  m->packed_stale = true;
   return BESSEL_OK;
 }
 
@@ -681,6 +745,7 @@ extern "C" int bessel_mlp_train(bessel_mlp* m, const bessel_mlp_train_cfg* cfg, 
     k_mlp_adam<<<dim3((kNW + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->params, m->grad, m->adam_m, m->adam_s,
                                                                      m->adam_step, lr, cfg->beta1, cfg->beta2,
                                                                      cfg->adam_eps);
+    m->packed_stale = true;
     rc = check_launch("k_mlp_adam");
     if (rc) return rc;
   }
@@ -697,9 +762,21 @@ extern "C" int bessel_mlp_adam_step(bessel_mlp* m, const float* grad, float lr, 
   if (!m || !grad) return set_error(BESSEL_ERR_ARG, "NULL argument");
   hipStream_t st = (hipStream_t)hip_stream;
   m->adam_step += 1;
+  m->packed_stale = true;
   k_mlp_adam<<<dim3((kNW + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->params, grad, m->adam_m, m->adam_s,
                                                                    m->adam_step, lr, beta1, beta2, eps);
   return check_launch("k_mlp_adam");
+}
+
+// Rebuild the inference operands on the caller's stream if the parameters
+// changed since they were last built.
+static int refresh_packed(const bessel_mlp* mc, hipStream_t st) {
+  bessel_mlp* m = const_cast<bessel_mlp*>(mc);
+  if (!m->packed_stale) return BESSEL_OK;
+  k_mlp_pack<<<1, kBlock, 0, st>>>(m->params, m->packed);
+  const int rc = check_launch("k_mlp_pack");
+  if (rc == BESSEL_OK) m->packed_stale = false;
+  return rc;
 }
 
 extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v, const float* x, float* y, int mode,
@@ -711,10 +788,13 @@ extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v
   int rc = grid_for(n, grid);
   if (rc) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
-  if (mode == 0)
+  if (mode == 0) {
     k_mlp_forward_f32<<<grid, kBlock, 0, st>>>(m->params, n, v, x, y);
-  else
-    k_mlp_forward_mfma<<<grid, kBlock, 0, st>>>(m->params, n, v, x, y);
+  } else {
+    rc = refresh_packed(m, st);
+    if (rc) return rc;
+    k_mlp_forward_mfma<<<grid, kBlock, 0, st>>>(m->packed, n, v, x, y);
+  }
   return check_launch("k_mlp_forward");
 }
 
@@ -732,22 +812,24 @@ static int run_mlp(int64_t n, const float* v, const float* x, const float* go, f
   if (n > 0x7fffffffLL - 1) return set_error(BESSEL_ERR_ARG, "n too large for the learned-range worklist");
   rc = ensure(m->work, m->cap_work, n + 1, st, "worklist");
   if (rc) return rc;
+  rc = refresh_packed(m, st);
+  if (rc) return rc;
   k_zero_int<<<1, 1, 0, st>>>(m->work);
   switch (nbins) {
     case 64:
-      k_logk_mlp<GRAD, 64><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+      k_logk_mlp<GRAD, 64><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
                                                     m->work);
       break;
     case 128:
-      k_logk_mlp<GRAD, 128><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+      k_logk_mlp<GRAD, 128><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
                                                      m->work);
       break;
     case 256:
-      k_logk_mlp<GRAD, 256><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+      k_logk_mlp<GRAD, 256><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
                                                      m->work);
       break;
     default:
-      k_logk_mlp<GRAD, 0><<<grid, kBlock, 0, st>>>(m->params, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
+      k_logk_mlp<GRAD, 0><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
                                                    m->work);
       break;
   }

@@ -1,17 +1,21 @@
-"""Generate the polynomial coefficients of the device FP64 exponential.
+"""Generate the polynomial coefficients of the device FP64 exponentials.
 
-e^r on |r| <= ln(2)/2 is approximated by a degree-10 polynomial whose relative
-error is minimax (Remez exchange on the weight 1/e^r, in 50-digit mpmath),
-then rounded to double.  Prints the coefficients and the error of the rounded
-polynomial; the values are pasted into bessel_device.hpp.
+e^r on |r| <= ln(2)/2 is approximated by a polynomial of the given degree
+whose relative error is minimax (Remez exchange on the weight 1/e^r, in
+50-digit mpmath), then rounded to double.  Prints the coefficients and the
+error of the rounded polynomial; the values are pasted into bessel_device.hpp:
+degree 10 for exp_f64 (3.0e-16), degree 9 for the per-node exponential of the
+FP64 bins (about 1e-14, far below the 1e-12 the FP64 path is held to).
 
-    python paper_2108_11560_amd/csrc/gen_exp_poly.py
+    python paper_2108_11560_amd/csrc/gen_exp_poly.py [degree]
 """
+
+import sys
 
 import mpmath as mp
 
 mp.mp.dps = 50
-DEG = 10
+DEG = int(sys.argv[1]) if len(sys.argv) > 1 else 10
 A = mp.log(2) / 2
 
 

@@ -5,7 +5,9 @@
 * a trained predictor's log K against the CPU oracle, with its fallback rate;
 * forced fallbacks (from the host: weights that make every check fail) give
   outputs bitwise equal to the Newton path;
-* learned brackets that pass the check contain the exact truncation set.
+* learned brackets that pass the check contain the exact truncation set;
+* the gain: evals/s of the learned-range FP32 path against the plain FP64
+  method and against FP32 bins on the Newton bracket.
 """
 
 import numpy as np
@@ -218,3 +220,50 @@ def test_mlp_rejects_f64(mods, trained):
     v = torch.ones(4, dtype=torch.float64, device="cuda")
     with pytest.raises(bk.BesselError):
         bk.logk(v, v, range="mlp", mlp=mlp)
+
+
+def _evals_per_s(fn, n, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return n / (a.elapsed_time(b) * 1e-3 / reps)
+
+
+def test_learned_range_gain(mods, trained):
+    """What the trained network gains: evals/s of the FP32 learned-range path
+    against the plain FP64 method and against FP32 bins on the Newton bracket,
+    on 2^22 scale pairs at 128 bins, with its error against the FP64 path."""
+    bk, M = mods
+    mlp, _ = trained
+    n = 1 << 22
+    v, x, _ = workloads.scale_pairs(n, seed=21)
+    v32, x32 = dev32(v), dev32(x)
+    v64, x64 = v32.double(), x32.double()
+    go32 = dev32(workloads.upstream_grad(n, seed=22))
+    go64 = go32.double()
+    rate = {
+        "mlp_fwd": _evals_per_s(lambda: bk.logk(v32, x32, range="mlp", mlp=mlp), n),
+        "newton32_fwd": _evals_per_s(lambda: bk.logk(v32, x32), n),
+        "f64_fwd": _evals_per_s(lambda: bk.logk(v64, x64), n),
+        "mlp_fwd_bwd": _evals_per_s(lambda: bk.logk_dv_dx(v32, x32, grad_out=go32, range="mlp", mlp=mlp), n),
+        "newton32_fwd_bwd": _evals_per_s(lambda: bk.logk_dv_dx(v32, x32, grad_out=go32), n),
+        "f64_fwd_bwd": _evals_per_s(lambda: bk.logk_dv_dx(v64, x64, grad_out=go64), n),
+    }
+    fallback = mlp.fallback_count() / n
+    ref = bk.logk(v64, x64)
+    out = bk.logk(v32, x32, range="mlp", mlp=mlp)
+    err = float(((out.double() - ref).abs() / ref.abs().clamp_min(1.0)).max())
+    print({k: f"{r:.3e}" for k, r in rate.items()}, "fallback", fallback, "max err vs f64", err)
+    print("learned / FP64: fwd %.2fx, fwd+bwd %.2fx;  learned / FP32 Newton: fwd %.2fx, fwd+bwd %.2fx" % (
+        rate["mlp_fwd"] / rate["f64_fwd"], rate["mlp_fwd_bwd"] / rate["f64_fwd_bwd"],
+        rate["mlp_fwd"] / rate["newton32_fwd"], rate["mlp_fwd_bwd"] / rate["newton32_fwd_bwd"]))
+    assert err <= 1e-5
+    assert fallback <= 0.02
+    # against the plain FP64 method, at the FP32 error bar
+    assert rate["mlp_fwd"] >= 1.2 * rate["f64_fwd"]
+    assert rate["mlp_fwd_bwd"] >= 1.1 * rate["f64_fwd_bwd"]
