@@ -56,6 +56,8 @@ def _load():
         dp = ctypes.POINTER(ctypes.c_double)
         lib.oracle_logk_batch.argtypes = [ctypes.c_int64, dp, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_logk_batch.restype = ctypes.c_int
+        lib.oracle_logk_hess_batch.argtypes = [ctypes.c_int64, dp, dp, dp, ctypes.c_int]
+        lib.oracle_logk_hess_batch.restype = ctypes.c_int
         lib.oracle_range_exact.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_double, dp, dp, dp, dp, ctypes.c_int]
         lib.oracle_range_exact.restype = ctypes.c_int
         lib.oracle_method_batch.argtypes = [
@@ -104,6 +106,20 @@ def logk(v, x, deriv: bool = False, nthreads: int | None = None):
     if rc != 0:
         raise ValueError("oracle_logk_batch rejected its arguments")
     return (out, dv, dx) if deriv else out
+
+
+def logk_hess(v, x, nthreads: int | None = None):
+    """log K_v(x) with its first and second derivatives: an (n, 6) array of
+    log K, d/dv, d/dx, d2/dv2, d2/dx2, d2/dvdx of log K."""
+    lib = _load()
+    v, x = np.broadcast_arrays(_arr(v), _arr(x))
+    v, x = _arr(v), _arr(x)
+    n = v.size
+    out = np.empty((n, 6))
+    rc = lib.oracle_logk_hess_batch(n, _ptr(v), _ptr(x), _ptr(out), nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_logk_hess_batch rejected its arguments")
+    return out
 
 
 def range_exact(v, x, log_eps: float, nthreads: int | None = None):

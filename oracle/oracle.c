@@ -23,7 +23,8 @@
  *
  * Two families of entry points:
  *
- *  (1) oracle_logk_batch / oracle_range_exact: the plain definitions.  log K is
+ *  (1) oracle_logk_batch / oracle_logk_hess_batch / oracle_range_exact: the
+ *      plain definitions.  log K is
  *      the integral of Eq. (1) computed by adaptive Gauss-Legendre quadrature
  *      (not the paper's fixed-bin trapezoid), split at the exact peak of g and
  *      truncated where g has fallen 60 nats below the peak (neglected mass below
@@ -31,6 +32,13 @@
  *      companion integrals of Eq. (13) with the exp(-x cosh t) factor present:
  *        d/dv K = int t sinh(v t) exp(-x cosh t) dt,
  *        d/dx K = -int cosh(t) cosh(v t) exp(-x cosh t) dt.
+ *      The second derivatives differentiate these once more under the
+ *      integral (Eq. (13) with n + m = 2):
+ *        d2/dv2 K  = int t^2 cosh(v t) exp(-x cosh t) dt,
+ *        d2/dx2 K  = int cosh^2(t) cosh(v t) exp(-x cosh t) dt,
+ *        d2/dvdx K = -int t cosh(t) sinh(v t) exp(-x cosh t) dt,
+ *      and those of log K follow from K''/K - (K'/K)^2 and
+ *      K_vx/K - (K_v/K)(K_x/K).
  *      The peak and the level crossings are found by plain bisection.
  *
  *  (2) oracle_method_batch: Algorithms 1-3 and Eq. (int) of Section 2 in the
@@ -41,8 +49,9 @@
  *   x == 0                   -> log K = +inf, derivatives NaN;
  *   x == +inf                -> log K = -inf, derivatives NaN;
  *   |v| == inf, finite x > 0 -> log K = +inf, derivatives NaN;
- *   v < 0                    -> evaluated at |v| (K_{-v} = K_v), d/dv negated;
- *   v == 0                   -> d/dv log K = 0 exactly.
+ *   v < 0                    -> evaluated at |v| (K_{-v} = K_v), d/dv and
+ *                               d2/dvdx negated;
+ *   v == 0                   -> d/dv log K = d2/dvdx log K = 0 exactly.
  */
 #include <math.h>
 #include <stdint.h>
@@ -164,45 +173,59 @@ static void gl_init(void) {
 }
 
 /* ---------------------------------------------------------------------- */
-/* Adaptive quadrature of the three integrands, scaled by exp(-G):          */
-/*   I0 = int exp(g - G) dt                 (K_v(x) e^{-G})                 */
-/*   I1 = int t tanh(v t) exp(g - G) dt     (d/dv K_v(x) e^{-G}, v >= 0)    */
-/*   I2 = int cosh(t) exp(g - G) dt         (-d/dx K_v(x) e^{-G})           */
+/* Adaptive quadrature of up to six integrands, scaled by exp(-G):          */
+/*   I0 = int exp(g - G) dt                    (K_v(x) e^{-G})              */
+/*   I1 = int t tanh(v t) exp(g - G) dt        (d/dv K e^{-G}, v >= 0)      */
+/*   I2 = int cosh(t) exp(g - G) dt            (-d/dx K e^{-G})             */
+/*   I3 = int t^2 exp(g - G) dt                (d2/dv2 K e^{-G})            */
+/*   I4 = int cosh^2(t) exp(g - G) dt          (d2/dx2 K e^{-G})            */
+/*   I5 = int t cosh(t) tanh(v t) exp(g - G) dt (-d2/dvdx K e^{-G})         */
+/* (exp(g) = cosh(v t) exp(-x cosh t), so t tanh(v t) exp(g) is the          */
+/* t sinh(v t) exp(-x cosh t) of d/dv, and so on.)  `level` 0 integrates I0, */
+/* 1 also I1-I2, 2 all six.                                                  */
 /* ---------------------------------------------------------------------- */
+
+#define NQ 6
 
 typedef struct {
   ld v, x, G;
-  ld tol[3];
-  int want_deriv;
+  ld tol[NQ];
+  int level;
 } quad_ctx;
 
-static void gl_panel(const quad_ctx* c, ld a, ld b, ld r[3]) {
+static void gl_panel(const quad_ctx* c, ld a, ld b, ld r[NQ]) {
   ld mid = 0.5L * (a + b), hw = 0.5L * (b - a);
-  ld s0 = 0.0L, s1 = 0.0L, s2 = 0.0L;
+  ld s[NQ] = {0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L};
   for (int i = 0; i < GL_N; ++i) {
     ld t = mid + hw * gl_node[i];
     ld e = expl(g_vx(c->v, c->x, t) - c->G);
-    s0 += gl_wt[i] * e;
-    if (c->want_deriv) {
-      s1 += gl_wt[i] * t * tanhl(c->v * t) * e;
-      s2 += gl_wt[i] * coshl(t) * e;
+    s[0] += gl_wt[i] * e;
+    if (c->level >= 1) {
+      ld th = t * tanhl(c->v * t), ch = coshl(t);
+      s[1] += gl_wt[i] * th * e;
+      s[2] += gl_wt[i] * ch * e;
+      if (c->level >= 2) {
+        s[3] += gl_wt[i] * t * t * e;
+        s[4] += gl_wt[i] * ch * ch * e;
+        s[5] += gl_wt[i] * th * ch * e;
+      }
     }
   }
-  r[0] = hw * s0; r[1] = hw * s1; r[2] = hw * s2;
+  for (int k = 0; k < NQ; ++k) r[k] = hw * s[k];
 }
 
-static void gl_adapt(const quad_ctx* c, ld a, ld b, const ld whole[3], int depth, ld acc[3]) {
+static void gl_adapt(const quad_ctx* c, ld a, ld b, const ld whole[NQ], int depth, ld acc[NQ]) {
   ld m = 0.5L * (a + b);
-  ld left[3], right[3], fine[3];
+  ld left[NQ], right[NQ], fine[NQ];
   gl_panel(c, a, m, left);
   gl_panel(c, m, b, right);
   int ok = 1;
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < NQ; ++k) {
     fine[k] = left[k] + right[k];
     if (!(fabsl(fine[k] - whole[k]) <= c->tol[k])) ok = 0;
   }
   if (ok || depth >= 48 || m <= a || m >= b) {
-    for (int k = 0; k < 3; ++k) acc[k] += fine[k];
+    for (int k = 0; k < NQ; ++k) acc[k] += fine[k];
     return;
   }
   gl_adapt(c, a, m, left, depth + 1, acc);
@@ -214,27 +237,29 @@ static void gl_adapt(const quad_ctx* c, ld a, ld b, const ld whole[3], int depth
  * long double rounding floor of a 20-point sum), then every panel is refined
  * adaptively.  An accepted panel's two-half estimate is far more accurate than
  * its difference from the one-panel estimate. */
-static void integrate(quad_ctx* c, ld lo, ld tp, ld hi, ld out[3]) {
+static void integrate(quad_ctx* c, ld lo, ld tp, ld hi, ld out[NQ]) {
   const int P = 8;
-  ld est[3] = {0.0L, 0.0L, 0.0L};
+  ld est[NQ] = {0.0L, 0.0L, 0.0L, 0.0L, 0.0L, 0.0L};
   ld edges[2][2] = {{lo, tp}, {tp, hi}};
   for (int s = 0; s < 2; ++s) {
     ld a = edges[s][0], b = edges[s][1];
     if (!(b > a)) continue;
     for (int p = 0; p < P; ++p) {
-      ld r[3];
+      ld r[NQ];
       gl_panel(c, a + (b - a) * p / P, a + (b - a) * (p + 1) / P, r);
-      for (int k = 0; k < 3; ++k) est[k] += fabsl(r[k]);
+      for (int k = 0; k < NQ; ++k) est[k] += fabsl(r[k]);
     }
   }
-  for (int k = 0; k < 3; ++k) c->tol[k] = (est[k] > 0.0L) ? 4e-18L * est[k] : INFINITY;
-  out[0] = out[1] = out[2] = 0.0L;
+  for (int k = 0; k < NQ; ++k) {
+    c->tol[k] = (est[k] > 0.0L) ? 4e-18L * est[k] : INFINITY;
+    out[k] = 0.0L;
+  }
   for (int s = 0; s < 2; ++s) {
     ld a = edges[s][0], b = edges[s][1];
     if (!(b > a)) continue;
     for (int p = 0; p < P; ++p) {
       ld pa = a + (b - a) * p / P, pb = a + (b - a) * (p + 1) / P;
-      ld whole[3];
+      ld whole[NQ];
       gl_panel(c, pa, pb, whole);
       gl_adapt(c, pa, pb, whole, 0, out);
     }
@@ -244,13 +269,18 @@ static void integrate(quad_ctx* c, ld lo, ld tp, ld hi, ld out[3]) {
 /* Margin below the peak at which the oracle truncates the integral. */
 #define ORACLE_MARGIN 60.0L
 
-/* One element of the plain definition.  Writes log K, d/dv log K, d/dx log K. */
-static void logk_one(double vin, double xin, double* logk, double* dv, double* dx, int want_deriv) {
+/* One element of the plain definition: out[0] = log K; with level >= 1 also
+ * out[1] = d/dv log K, out[2] = d/dx log K; with level 2 also
+ * out[3] = d2/dv2 log K, out[4] = d2/dx2 log K, out[5] = d2/dvdx log K. */
+static void logk_one(double vin, double xin, int level, double out[NQ]) {
+  const int nout = level == 0 ? 1 : level == 1 ? 3 : NQ;
   ld nan_ = NAN;
-  if (isnan(vin) || isnan(xin) || xin < 0.0) { *logk = nan_; if (want_deriv) { *dv = nan_; *dx = nan_; } return; }
-  if (xin == 0.0) { *logk = INFINITY; if (want_deriv) { *dv = nan_; *dx = nan_; } return; }
-  if (isinf(xin)) { *logk = -INFINITY; if (want_deriv) { *dv = nan_; *dx = nan_; } return; }
-  if (isinf(vin)) { *logk = INFINITY; if (want_deriv) { *dv = nan_; *dx = nan_; } return; }
+  if (isnan(vin) || isnan(xin) || xin < 0.0 || xin == 0.0 || isinf(xin) || isinf(vin)) {
+    out[0] = (isnan(vin) || isnan(xin) || xin < 0.0) ? nan_
+             : (xin == 0.0) ? INFINITY : isinf(xin) ? -INFINITY : INFINITY;
+    for (int k = 1; k < nout; ++k) out[k] = nan_;
+    return;
+  }
   ld sgn = (vin < 0.0) ? -1.0L : 1.0L;
   ld v = fabsl((ld)vin), x = (ld)xin;
   ld tp = exact_peak(v, x);
@@ -258,13 +288,19 @@ static void logk_one(double vin, double xin, double* logk, double* dv, double* d
   ld lo = lower_cross(v, x, tp, G, ORACLE_MARGIN);
   ld hi = upper_cross(v, x, tp, G, ORACLE_MARGIN);
   quad_ctx c;
-  c.v = v; c.x = x; c.G = G; c.want_deriv = want_deriv;
-  ld I[3];
+  c.v = v; c.x = x; c.G = G; c.level = level;
+  ld I[NQ];
   integrate(&c, lo, tp, hi, I);
-  *logk = (double)(G + logl(I[0]));
-  if (want_deriv) {
-    *dv = (v == 0.0L) ? 0.0 : (double)(sgn * I[1] / I[0]);
-    *dx = (double)(-I[2] / I[0]);
+  out[0] = (double)(G + logl(I[0]));
+  if (level >= 1) {
+    ld lv = I[1] / I[0], lx = -I[2] / I[0];
+    out[1] = (v == 0.0L) ? 0.0 : (double)(sgn * lv);
+    out[2] = (double)lx;
+    if (level >= 2) {
+      out[3] = (double)(I[3] / I[0] - lv * lv);
+      out[4] = (double)(I[4] / I[0] - lx * lx);
+      out[5] = (v == 0.0L) ? 0.0 : (double)(sgn * (-I[5] / I[0] - lv * lx));
+    }
   }
 }
 
@@ -313,11 +349,12 @@ typedef struct { const double *v, *x; double *logk, *dv, *dx; } logk_args;
 
 static void logk_elem(void* ctx, int64_t i) {
   logk_args* a = (logk_args*)ctx;
-  double d0 = 0.0, d1 = 0.0;
+  double o[NQ];
   int want = (a->dv != NULL) || (a->dx != NULL);
-  logk_one(a->v[i], a->x[i], &a->logk[i], &d0, &d1, want);
-  if (a->dv) a->dv[i] = d0;
-  if (a->dx) a->dx[i] = d1;
+  logk_one(a->v[i], a->x[i], want ? 1 : 0, o);
+  a->logk[i] = o[0];
+  if (a->dv) a->dv[i] = o[1];
+  if (a->dx) a->dx[i] = o[2];
 }
 
 /* log K_v(x) for n pairs; dv and dx (nullable) receive d/dv and d/dx of log K. */
@@ -326,6 +363,22 @@ int oracle_logk_batch(int64_t n, const double* v, const double* x, double* logk,
   if (n < 0 || (n > 0 && (!v || !x || !logk))) return -1;
   logk_args a = {v, x, logk, dv, dx};
   run_pool(logk_elem, &a, n, nthreads);
+  return 0;
+}
+
+typedef struct { const double *v, *x; double* out; } hess_args;
+
+static void hess_elem(void* ctx, int64_t i) {
+  hess_args* a = (hess_args*)ctx;
+  logk_one(a->v[i], a->x[i], 2, a->out + NQ * i);
+}
+
+/* log K and its first and second derivatives for n pairs: out[6 i + k] holds
+ * log K, d/dv, d/dx, d2/dv2, d2/dx2, d2/dvdx of log K at (v[i], x[i]). */
+int oracle_logk_hess_batch(int64_t n, const double* v, const double* x, double* out, int nthreads) {
+  if (n < 0 || (n > 0 && (!v || !x || !out))) return -1;
+  hess_args a = {v, x, out};
+  run_pool(hess_elem, &a, n, nthreads);
   return 0;
 }
 
