@@ -10,8 +10,10 @@ resident in HBM before timing.  Each path is timed over the whole batch at
     f32_mlp_fwd_bwd  the same with d/dv, d/dx log K times an upstream gradient
     f64_fwd          the plain method in FP64 (Newton bracket), log K
     f64_fwd_bwd
+    f64_hess         log K with first and second derivatives, FP64
     f32_fwd          FP32 bins on the Newton bracket
     f32_fwd_bwd
+    f32_hess
     gh_f32_fwd_bwd   per-set sums over 1024 sets x 65536 samples with gradients
 
 The predictor is trained (20000 Adam steps on 2^20 Newton brackets) and its
@@ -42,7 +44,10 @@ import workloads  # noqa: E402
 # instruction on one lane = 1 slot; an FP32 transcendental = 2, measured half
 # rate; v_rcp_f64 = 4):  W(n) = (n + 1) * W_NODE + W_PRE, from the operation
 # count of the formulation (one table per path in DESIGN.md, "Roofline").
-W_NODE = {("f32", False): 9.0, ("f32", True): 15.0, ("f64", False): 24.5, ("f64", True): 30.5}
+# keyed by (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2 with the
+# second derivatives too
+W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
+          ("f64", 0): 24.5, ("f64", 1): 30.5, ("f64", 2): 36.5}
 W_PRE = 500.0
 # Learned bracket: the network's VALU work (128 activations 1 / (1 + 2^a) at
 # 5 slots, 128 layer-3 FMAs, features 6, bf16 packing 32, outputs 4; its 48
@@ -75,14 +80,14 @@ def kernel_sources_sha256() -> str:
     return h.hexdigest()
 
 
-def alg_slots(dt: str, grad: bool, nbins: int) -> float:
-    return (nbins + 1) * W_NODE[(dt, grad)] + W_PRE
+def alg_slots(dt: str, der: int, nbins: int) -> float:
+    return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE
 
 
 def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float) -> float:
     """Per element of a learned-range call: the fused kernel's work, plus the
     Newton path for the fallback fraction."""
-    return (nbins + 1) * W_NODE[("f32", grad)] + W_MLP_PRE + fallback_rate * alg_slots("f32", grad, nbins)
+    return (nbins + 1) * W_NODE[("f32", int(grad))] + W_MLP_PRE + fallback_rate * alg_slots("f32", grad, nbins)
 
 
 def parse():
@@ -212,6 +217,9 @@ def main():
         ms_b = time_path(fb, args.steps, args.warmup)
         paths[f"{dt}_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3)}
         paths[f"{dt}_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3)}
+        hs = lambda dt=dt: bk.logk_hess(V[dt], X[dt], nbins=nb)  # noqa: E731
+        ms_h = time_path(hs, max(1, args.steps // 2), args.warmup)
+        paths[f"{dt}_hess"] = {"ms": ms_h, "evals_per_s": args.n / (ms_h * 1e-3)}
 
     fwd = lambda: bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
     fb = lambda: bk.logk_dv_dx(V["f32"], X["f32"], grad_out=GO["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
@@ -238,11 +246,11 @@ def main():
     for key, p in paths.items():
         if key.startswith("gh"):
             continue
-        grad = key.endswith("bwd")
+        der = 2 if key.endswith("hess") else 1 if key.endswith("bwd") else 0
         if "mlp" in key:
-            p["alg_slots_per_elem"] = alg_slots_mlp(grad, nb, p["fallback_rate"])
+            p["alg_slots_per_elem"] = alg_slots_mlp(der == 1, nb, p["fallback_rate"])
         else:
-            p["alg_slots_per_elem"] = alg_slots(key[:3], grad, nb)
+            p["alg_slots_per_elem"] = alg_slots(key[:3], der, nb)
         p["valu_frac"] = p["alg_slots_per_elem"] * p["evals_per_s"] / PEAK_SLOTS
 
     head = paths["f32_mlp_fwd"]

@@ -103,6 +103,36 @@ int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, v
                  uint8_t* fallback, void* hip_stream);
 
 /*
+ * bessel_logk_hess -- log K with its first and second derivatives in v and x
+ * from one pass over the same bins (Section 4.1, Eq. (13) with n + m <= 2:
+ * the integrands t^2 f, cosh^2(t) f and t cosh(t) sinh(vt) e^{-x cosh t}
+ * join those of the first derivatives):
+ *   dvv[i] = d2/dv2 log K = K_vv/K - (K_v/K)^2,
+ *   dxx[i] = d2/dx2 log K = K_xx/K - (K_x/K)^2,
+ *   dvx[i] = d2/dvdx log K = K_vx/K - (K_v/K)(K_x/K),
+ * and logk, dv, dx as bessel_logk_dv_dx.  Every output is nullable (at least
+ * one must be given); outputs may not overlap inputs or each other.  Newton
+ * bracket, dtype F32 or F64.  Conventions: K_{-v} = K_v, so dv and dvx are odd
+ * in v (0 at v = 0) and dvv, dxx even; special inputs give NaN derivatives.
+ */
+int bessel_logk_hess(int dtype, int64_t n, const void* v, const void* x, void* logk, void* dv, void* dx, void* dvv,
+                     void* dxx, void* dvx, int nbins, void* hip_stream);
+
+/*
+ * bessel_hess_vjp -- the backward step through (d/dv, d/dx) log K, with the
+ * second derivatives a bessel_logk_hess call produced (the Hessian of log K is
+ * symmetric):
+ *   grad_v[i] = g_dv[i] dvv[i] + g_dx[i] dvx[i],
+ *   grad_x[i] = g_dv[i] dvx[i] + g_dx[i] dxx[i].
+ * g_dv or g_dx may be NULL (a zero upstream gradient), not both; grad_v or
+ * grad_x may be NULL (not needed).  Outputs may not overlap inputs.  This is
+ * what second-order differentiation (a Newton step in v or x, a Hessian of a
+ * likelihood) needs from Section 4.1's derivatives.
+ */
+int bessel_hess_vjp(int dtype, int64_t n, const void* g_dv, const void* g_dx, const void* dvv, const void* dxx,
+                    const void* dvx, void* grad_v, void* grad_x, void* hip_stream);
+
+/*
  * bessel_logk_backward -- the backward step of a scalar loss through log K:
  *   grad_v[i] = grad_out[i] * dv[i],  grad_x[i] = grad_out[i] * dx[i],
  * where dv, dx are the derivatives a forward bessel_logk_dv_dx call saved.

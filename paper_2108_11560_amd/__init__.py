@@ -14,8 +14,10 @@ computation runs in the library's kernels.
 
     logk(v, x, nbins=128)                  -> log K_v(x)
     logk_dv_dx(v, x, grad_out=None, ...)   -> (log K, d/dv log K, d/dx log K)
+    logk_hess(v, x)                        -> (log K, d/dv, d/dx, d2/dv2, d2/dx2, d2/dvdx)
     bessel_range(v, x)                     -> (t0, t1, t_p, g(t_p))
-    log_bessel_k(v, x)                     -> log K with autograd (BesselLogK)
+    log_bessel_k(v, x)                     -> log K with autograd (BesselLogK),
+                                              twice differentiable on the Newton bracket
 """
 
 from __future__ import annotations
@@ -30,6 +32,7 @@ from ._lib import F32, F64, RANGE_MLP, RANGE_NEWTON, BesselError, check, load  #
 __all__ = [
     "logk",
     "logk_dv_dx",
+    "logk_hess",
     "bessel_range",
     "log_bessel_k",
     "gh_logk_sum",
@@ -114,6 +117,19 @@ def logk_dv_dx(v: torch.Tensor, x: torch.Tensor, grad_out: torch.Tensor | None =
     return lk, dv, dx
 
 
+def logk_hess(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, want=(True,) * 6):
+    """(log K, d/dv, d/dx, d2/dv2, d2/dx2, d2/dvdx) of log K from one pass
+    (Newton bracket); an output whose ``want`` flag is False comes back None."""
+    v, x = _check_pair(v, x)
+    outs = [torch.empty_like(v) if w else None for w in want]
+    lib = load()
+    with torch.cuda.device(v.device):
+        rc = lib.bessel_logk_hess(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), *(_ptr(o) for o in outs), int(nbins),
+                                  _stream_ptr(v.device))
+    check(rc, "bessel_logk_hess")
+    return tuple(outs)
+
+
 def bessel_range(v: torch.Tensor, x: torch.Tensor, range: str = "newton", mlp=None, want_fallback: bool = False):
     """Integration range (t0, t1), peak t_p and g(t_p) per element (and the fallback flags)."""
     v, x = _check_pair(v, x)
@@ -152,26 +168,69 @@ def gh_logk_sum(lam: torch.Tensor, alpha: torch.Tensor, delta: torch.Tensor, mu:
     return (out, *grads) if want_grad else out
 
 
+class _BesselDLogK(torch.autograd.Function):
+    """(d/dv log K, d/dx log K) as a differentiable function of (v, x): the
+    forward runs ``bessel_logk_hess`` (first and second derivatives from one
+    pass), the backward ``bessel_hess_vjp`` with the saved second derivatives."""
+
+    @staticmethod
+    def forward(ctx, v, x, nbins):
+        _, dv, dx, dvv, dxx, dvx = logk_hess(v, x, nbins=nbins, want=(False, True, True, True, True, True))
+        ctx.save_for_backward(dvv, dxx, dvx)
+        return dv, dx
+
+    @staticmethod
+    @torch.autograd.function.once_differentiable
+    def backward(ctx, g_dv, g_dx):
+        dvv, dxx, dvx = ctx.saved_tensors
+        g_dv = g_dv.contiguous() if g_dv is not None else None
+        g_dx = g_dx.contiguous() if g_dx is not None else None
+        gv = torch.empty_like(dvv) if ctx.needs_input_grad[0] else None
+        gx = torch.empty_like(dvv) if ctx.needs_input_grad[1] else None
+        if gv is None and gx is None:
+            return None, None, None
+        if g_dv is None and g_dx is None:
+            return (torch.zeros_like(dvv) if gv is not None else None,
+                    torch.zeros_like(dvv) if gx is not None else None, None)
+        lib = load()
+        with torch.cuda.device(dvv.device):
+            rc = lib.bessel_hess_vjp(_dtype_code(dvv), dvv.numel(), _ptr(g_dv), _ptr(g_dx), _ptr(dvv), _ptr(dxx),
+                                     _ptr(dvx), _ptr(gv), _ptr(gx), _stream_ptr(dvv.device))
+        check(rc, "bessel_hess_vjp")
+        return gv, gx, None
+
+
 class BesselLogK(torch.autograd.Function):
     """log K_v(x) with a hand-written backward.
 
     The forward runs the fused kernel that also produces d/dv and d/dx of log K
     from the same bins whenever an input needs a gradient; backward multiplies
     the saved derivatives by the upstream gradient in the library's
-    ``bessel_logk_backward`` kernel.
+    ``bessel_logk_backward`` kernel.  Under ``create_graph`` (second-order
+    differentiation, Newton bracket only) the backward instead builds its
+    result from :class:`_BesselDLogK`, whose own backward uses the second
+    derivatives of the same bins.
     """
 
     @staticmethod
     def forward(ctx, v, x, nbins=128, range="newton", mlp=None):
+        ctx.nbins, ctx.range = nbins, range
         if ctx.needs_input_grad[0] or ctx.needs_input_grad[1]:
             lk, dv, dx = logk_dv_dx(v, x, None, nbins=nbins, range=range, mlp=mlp)
-            ctx.save_for_backward(dv, dx)
+            ctx.save_for_backward(v, x, dv, dx)
             return lk
         return logk(v, x, nbins=nbins, range=range, mlp=mlp)
 
     @staticmethod
     def backward(ctx, go):
-        dv, dx = ctx.saved_tensors
+        v, x, dv, dx = ctx.saved_tensors
+        if torch.is_grad_enabled():
+            if ctx.range != "newton":
+                raise BesselError("second-order differentiation needs the Newton bracket")
+            dvt, dxt = _BesselDLogK.apply(v, x, ctx.nbins)
+            gv = go * dvt if ctx.needs_input_grad[0] else None
+            gx = go * dxt if ctx.needs_input_grad[1] else None
+            return gv, gx, None, None, None
         go = go.contiguous()
         gv = torch.empty_like(dv) if ctx.needs_input_grad[0] else None
         gx = torch.empty_like(dx) if ctx.needs_input_grad[1] else None
@@ -184,7 +243,7 @@ class BesselLogK(torch.autograd.Function):
 
 
 def log_bessel_k(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, range: str = "newton", mlp=None):
-    """log K_v(x) with autograd support in v and x."""
+    """log K_v(x) with autograd support in v and x (second order on the Newton bracket)."""
     if v.shape != x.shape:
         v, x = torch.broadcast_tensors(v, x)
     return BesselLogK.apply(v, x, nbins, range, mlp)

@@ -37,6 +37,8 @@ SIGNATURES = {
     "bessel_logk_dv_dx": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _int, _int, _vp, _vp]),
     "bessel_range": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp, _vp, _vp]),
     "bessel_logk_backward": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bessel_logk_hess": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
+    "bessel_hess_vjp": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bessel_mlp_create": (_int, [_vp, _i64, _vp]),
     "bessel_mlp_destroy": (_int, [_vp]),
     "bessel_mlp_set_params": (_int, [_vp, _vp, _i64]),

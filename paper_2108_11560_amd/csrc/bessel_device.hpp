@@ -189,12 +189,16 @@ __device__ __forceinline__ bool domain_special(double v, double x, double& logk,
     logk = nan_; dv = nan_; dx = nan_;
     return true;
   }
-  if (x == 0.0 || __builtin_isinf(v)) {
+  if (x == 0.0) {
     logk = __builtin_inf(); dv = nan_; dx = nan_;
     return true;
   }
   if (__builtin_isinf(x)) {
     logk = -__builtin_inf(); dv = nan_; dx = nan_;
+    return true;
+  }
+  if (__builtin_isinf(v)) {
+    logk = __builtin_inf(); dv = nan_; dx = nan_;
     return true;
   }
   return false;
@@ -326,6 +330,8 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
 // ---------------------------------------------------------------------------
 struct BinSums {
   double S0, Sv, Sx;
+  // second-derivative sums (DER == 2): t^2 f, cosh^2 t f, t cosh t sinh(vt) e^{-x cosh t}
+  double Svv, Sxx, Svx;
   // Filled only by the checked FP32 variant (learned brackets): the sums over
   // even and over odd nodes (each a trapezoid / midpoint rule of step 2h; their
   // difference measures the quadrature error), and the unweighted terms at the
@@ -342,8 +348,10 @@ constexpr int kChunk32 = 32;  // nodes per unrolled chunk (FP32 bins)
 // ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).  f at a node
 // is e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the
 // FP32 bins); even and odd nodes are summed apart (independent FMA chains).
-template <bool GRAD>
+// DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums.
+template <int DER>
 __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1) {
+  constexpr bool GRAD = DER >= 1;
   const double h = (t1 - t0) / (double)nb;
   const double Gs = G + kLn2;
   const double xh = 0.5 * x;
@@ -352,8 +360,9 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
   double u = 2.0 - r;
-  BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+  BinSums s{};
   double S[2] = {0.0, 0.0}, Sv[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0};
+  double Svv[2] = {0.0, 0.0}, Sxx[2] = {0.0, 0.0}, Svx[2] = {0.0, 0.0};
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
@@ -367,8 +376,14 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
       if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
       S[b & 1] = fma(w, u, S[b & 1]);
       if (GRAD) {
-        Sv[b & 1] = fma(w * r, t, Sv[b & 1]);
-        Sx[b & 1] = fma(w * u, 0.5 * ch2, Sx[b & 1]);
+        const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
+        Sv[b & 1] = fma(wr, t, Sv[b & 1]);
+        Sx[b & 1] = fma(wu, ch, Sx[b & 1]);
+        if (DER >= 2) {
+          Svv[b & 1] = fma(wu * t, t, Svv[b & 1]);
+          Sxx[b & 1] = fma(wu * ch, ch, Sxx[b & 1]);
+          Svx[b & 1] = fma(wr * t, ch, Svx[b & 1]);
+        }
         r = fma(r, Q, E2);
       }
       u = fma(u, Q, E2);
@@ -385,8 +400,14 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
     if (m == 0 || m == nb) w *= 0.5;
     S[m & 1] = fma(w, u, S[m & 1]);
     if (GRAD) {
-      Sv[m & 1] = fma(w * r, t, Sv[m & 1]);
-      Sx[m & 1] = fma(w * u, 0.5 * ch2, Sx[m & 1]);
+      const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
+      Sv[m & 1] = fma(wr, t, Sv[m & 1]);
+      Sx[m & 1] = fma(wu, ch, Sx[m & 1]);
+      if (DER >= 2) {
+        Svv[m & 1] = fma(wu * t, t, Svv[m & 1]);
+        Sxx[m & 1] = fma(wu * ch, ch, Sxx[m & 1]);
+        Svx[m & 1] = fma(wr * t, ch, Svx[m & 1]);
+      }
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -395,6 +416,11 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   if (GRAD) {
     s.Sv = Sv[0] + Sv[1];
     s.Sx = Sx[0] + Sx[1];
+  }
+  if (DER >= 2) {
+    s.Svv = Svv[0] + Svv[1];
+    s.Sxx = Sxx[0] + Sxx[1];
+    s.Svx = Svx[0] + Svx[1];
   }
   return s;
 }
@@ -410,8 +436,9 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
 // r (for d/dv) is kept by its own recurrence rather than as 2 - u, which would
 // lose its relative accuracy as v -> 0.  The forward and derivative variants
 // accumulate S0 with identical operations.
-template <bool GRAD, bool CHECK = false>
+template <int DER, bool CHECK = false>
 __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G, double t0, double t1) {
+  constexpr bool GRAD = DER >= 1;
   const double h = (t1 - t0) / (double)nb;
   const double vl = v * kLog2e;
   const double xl = x * kLog2e;
@@ -429,10 +456,11 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   double r = one_minus_exp_neg(2.0 * v * t0);
   double u = 2.0 - r;
   const double L0 = fma(vl, t0, -Gl);  // (v t - G - log 2) log2 e
-  BinSums s{0.0, 0.0, 0.0, 0.0, 0.0, 0.0f, 0.0f};
+  BinSums s{};
   // even and odd nodes go to separate sums (two independent FMA chains; the
   // checked variant also needs them apart); chunk starts are even
   double S[2] = {0.0, 0.0}, Sv[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0};
+  double Svv[2] = {0.0, 0.0}, Sxx[2] = {0.0, 0.0}, Svx[2] = {0.0, 0.0};
   const int nchunks = nb / kChunk32;
   for (int c = 0; c < nchunks; ++c) {
     // the linear part runs by addition inside a chunk (error <= kChunk32 ulp of |L|)
@@ -446,8 +474,14 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
       const double wd = (double)w;
       S[b & 1] = fma(wd, u, S[b & 1]);
       if (GRAD) {
-        Sv[b & 1] = fma(wd * r, fma((double)b, h, ta), Sv[b & 1]);
-        Sx[b & 1] = fma(wd * u, C, Sx[b & 1]);
+        const double t = fma((double)b, h, ta), wr = wd * r, wu = wd * u;
+        Sv[b & 1] = fma(wr, t, Sv[b & 1]);
+        Sx[b & 1] = fma(wu, C, Sx[b & 1]);
+        if (DER >= 2) {
+          Svv[b & 1] = fma(wu * t, t, Svv[b & 1]);
+          Sxx[b & 1] = fma(wu * C, C, Sxx[b & 1]);
+          Svx[b & 1] = fma(wr * t, C, Svx[b & 1]);
+        }
         r = fma(r, Q, E2);
       }
       u = fma(u, Q, E2);
@@ -466,9 +500,14 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
     const double wd = (double)w;
     S[m & 1] = fma(wd, u, S[m & 1]);
     if (GRAD) {
-      const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-      Sv[m & 1] = fma(wd * r, t, Sv[m & 1]);
-      Sx[m & 1] = fma(wd * u, C, Sx[m & 1]);
+      const double t = (m == nb) ? t1 : fma((double)m, h, t0), wr = wd * r, wu = wd * u;
+      Sv[m & 1] = fma(wr, t, Sv[m & 1]);
+      Sx[m & 1] = fma(wu, C, Sx[m & 1]);
+      if (DER >= 2) {
+        Svv[m & 1] = fma(wu * t, t, Svv[m & 1]);
+        Sxx[m & 1] = fma(wu * C, C, Sxx[m & 1]);
+        Svx[m & 1] = fma(wr * t, C, Svx[m & 1]);
+      }
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -484,6 +523,11 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   if (GRAD) {
     s.Sv = Sv[0] + Sv[1];
     s.Sx = Sx[0] + Sx[1];
+  }
+  if (DER >= 2) {
+    s.Svv = Svv[0] + Svv[1];
+    s.Sxx = Sxx[0] + Sxx[1];
+    s.Svx = Svx[0] + Svx[1];
   }
   return s;
 }

@@ -28,12 +28,12 @@ __device__ __forceinline__ float margin_of() {
   return sizeof(T) == 8 ? kMarginF64 : kMarginF32;
 }
 
-template <typename T, bool GRAD>
+template <typename T, int DER>
 __device__ __forceinline__ BinSums run_bins(int nb, double v, double x, const Bracket& b) {
   if constexpr (sizeof(T) == 8) {
-    return bins_f64<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+    return bins_f64<DER>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
   } else {
-    return bins_f32<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+    return bins_f32<DER>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
   }
 }
 
@@ -52,7 +52,7 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
   if (!domain_special(vs, x, lk, dvv, dxv)) {
     const double v = fabs(vs);
     const Bracket b = find_bracket(v, x, margin_of<T>());
-    const BinSums s = run_bins<T, GRAD>(nb, v, x, b);
+    const BinSums s = run_bins<T, GRAD ? 1 : 0>(nb, v, x, b);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
     const double rS0 = rcp_f64(s.S0);
     lk = b.G + log_f64(h * s.S0);
@@ -73,6 +73,46 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
   } else {
     logk[i] = (T)lk;
   }
+}
+
+// log K with its first and second derivatives in v and x from one pass over
+// the bins (Section 4.1, Eq. (13) with n + m <= 2):
+//   d2/dv2 log K = S_vv/S - (S_v/S)^2,  d2/dx2 log K = S_xx/S - (S_x/S)^2,
+//   d2/dvdx log K = -S_vx/S + (S_v/S)(S_x/S)   (odd in v, like d/dv).
+// Every output is nullable.
+template <typename T, int NB>
+__global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, const T* __restrict__ vin,
+                                                      const T* __restrict__ xin, T* __restrict__ logk,
+                                                      T* __restrict__ dv, T* __restrict__ dx, T* __restrict__ dvv,
+                                                      T* __restrict__ dxx, T* __restrict__ dvx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const int nb = NB > 0 ? NB : nbins;
+  const double vs = (double)vin[i];
+  const double x = (double)xin[i];
+  double lk, lv, lx;
+  double lvv = __builtin_nan(""), lxx = __builtin_nan(""), lvx = __builtin_nan("");
+  if (!domain_special(vs, x, lk, lv, lx)) {
+    const double v = fabs(vs);
+    const Bracket b = find_bracket(v, x, margin_of<T>());
+    const BinSums s = run_bins<T, 2>(nb, v, x, b);
+    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+    const double rS0 = rcp_f64(s.S0);
+    const double ev = s.Sv * rS0, ex = s.Sx * rS0;
+    lk = b.G + log_f64(h * s.S0);
+    lv = (v == 0.0) ? 0.0 : copysign(ev, vs);
+    lx = -ex;
+    lvv = fma(-ev, ev, s.Svv * rS0);
+    lxx = fma(-ex, ex, s.Sxx * rS0);
+    const double mvx = fma(ev, ex, -s.Svx * rS0);  // any sign: flip it for v < 0, do not replace it
+    lvx = (v == 0.0) ? 0.0 : (vs < 0.0 ? -mvx : mvx);
+  }
+  if (logk) logk[i] = (T)lk;
+  if (dv) dv[i] = (T)lv;
+  if (dx) dx[i] = (T)lx;
+  if (dvv) dvv[i] = (T)lvv;
+  if (dxx) dxx[i] = (T)lxx;
+  if (dvx) dvx[i] = (T)lvx;
 }
 
 template <typename T>
@@ -108,6 +148,23 @@ __global__ __launch_bounds__(kBlock) void k_backward(int64_t n, const T* __restr
   const T g = go[i];
   if (gv) gv[i] = g * dv[i];
   if (gx) gx[i] = g * dx[i];
+}
+
+// Vector-Jacobian product of (d/dv, d/dx) log K with the symmetric Hessian:
+//   grad_v = g_dv dvv + g_dx dvx,  grad_x = g_dv dvx + g_dx dxx  (either output,
+//   and either upstream gradient, may be NULL).
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_hess_vjp(int64_t n, const T* __restrict__ gdv, const T* __restrict__ gdx,
+                                                     const T* __restrict__ dvv, const T* __restrict__ dxx,
+                                                     const T* __restrict__ dvx, T* __restrict__ gv,
+                                                     T* __restrict__ gx) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const T a = gdv ? gdv[i] : (T)0;
+  const T b = gdx ? gdx[i] : (T)0;
+  const T m = dvx[i];
+  if (gv) gv[i] = gdx ? (gdv ? fma(a, dvv[i], b * m) : b * m) : a * dvv[i];
+  if (gx) gx[i] = gdv ? (gdx ? fma(a, m, b * dxx[i]) : a * m) : b * dxx[i];
 }
 
 // ---------------------------------------------------------------------------
@@ -177,6 +234,20 @@ int logk_newton(int dtype, int64_t n, const void* v, const void* x, const void* 
                                 nullptr);
   }
   return check_launch("k_logk");
+}
+
+template <typename T>
+static void launch_hess(dim3 grid, hipStream_t st, int64_t n, int nbins, const void* v, const void* x, void* const* o) {
+  const T* vv = (const T*)v;
+  const T* xx = (const T*)x;
+  T* p[6];
+  for (int k = 0; k < 6; ++k) p[k] = (T*)o[k];
+  switch (nbins) {
+    case 64: k_logk_hess<T, 64><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+    case 128: k_logk_hess<T, 128><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+    case 256: k_logk_hess<T, 256><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+    default: k_logk_hess<T, 0><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+  }
 }
 
 int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp, void* gpk,
@@ -256,6 +327,35 @@ extern "C" int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void
   return logk_newton(dtype, n, v, x, grad_out, logk, dv, dx, nbins, true, st);
 }
 
+extern "C" int bessel_logk_hess(int dtype, int64_t n, const void* v, const void* x, void* logk, void* dv, void* dx,
+                                void* dvv, void* dxx, void* dvx, int nbins, void* hip_stream) {
+  int rc = common_checks(dtype, n, v, x, BESSEL_RANGE_NEWTON, nullptr);
+  if (rc) return rc;
+  if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
+    return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
+  if (n == 0) return BESSEL_OK;
+  void* outs[6] = {logk, dv, dx, dvv, dxx, dvx};
+  bool any = false;
+  for (void* o : outs) any = any || (o != nullptr);
+  if (!any) return set_error(BESSEL_ERR_ARG, "at least one output must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  for (int a = 0; a < 6; ++a) {
+    if (overlaps(outs[a], nb, v, nb) || overlaps(outs[a], nb, x, nb))
+      return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+    for (int b = a + 1; b < 6; ++b)
+      if (overlaps(outs[a], nb, outs[b], nb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
+  }
+  dim3 grid;
+  rc = grid_for(n, grid);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (dtype == BESSEL_F64)
+    launch_hess<double>(grid, st, n, nbins, v, x, outs);
+  else
+    launch_hess<float>(grid, st, n, nbins, v, x, outs);
+  return check_launch("k_logk_hess");
+}
+
 extern "C" int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp,
                             void* logf_peak, int range_mode, const bessel_mlp* mlp, uint8_t* fallback,
                             void* hip_stream) {
@@ -305,6 +405,34 @@ extern "C" int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, 
     k_backward<float><<<grid, kBlock, 0, st>>>(n, (const float*)grad_out, (const float*)dv, (const float*)dx,
                                                (float*)grad_v, (float*)grad_x);
   return check_launch("k_backward");
+}
+
+extern "C" int bessel_hess_vjp(int dtype, int64_t n, const void* g_dv, const void* g_dx, const void* dvv,
+                               const void* dxx, const void* dvx, void* grad_v, void* grad_x, void* hip_stream) {
+  if (dtype != BESSEL_F32 && dtype != BESSEL_F64) return set_error(BESSEL_ERR_DTYPE, "dtype %d is not F32/F64", dtype);
+  if (n < 0) return set_error(BESSEL_ERR_ARG, "n = %lld < 0", (long long)n);
+  if (n == 0) return BESSEL_OK;
+  if (!g_dv && !g_dx) return set_error(BESSEL_ERR_ARG, "g_dv and g_dx cannot both be NULL");
+  if (!dvx || (g_dv && grad_v && !dvv) || (g_dx && grad_x && !dxx))
+    return set_error(BESSEL_ERR_ARG, "dvx, and dvv/dxx where they are used, must be non-NULL");
+  const size_t nb = (size_t)n * elem_size(dtype);
+  const void* ins[5] = {g_dv, g_dx, dvv, dxx, dvx};
+  for (int b = 0; b < 5; ++b)
+    if (overlaps(grad_v, nb, ins[b], nb) || overlaps(grad_x, nb, ins[b], nb))
+      return set_error(BESSEL_ERR_ALIAS, "an output overlaps an input");
+  if (overlaps(grad_v, nb, grad_x, nb)) return set_error(BESSEL_ERR_ALIAS, "grad_v overlaps grad_x");
+  dim3 grid;
+  int rc = grid_for(n, grid);
+  if (rc) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  if (dtype == BESSEL_F64)
+    k_hess_vjp<double><<<grid, kBlock, 0, st>>>(n, (const double*)g_dv, (const double*)g_dx, (const double*)dvv,
+                                                (const double*)dxx, (const double*)dvx, (double*)grad_v,
+                                                (double*)grad_x);
+  else
+    k_hess_vjp<float><<<grid, kBlock, 0, st>>>(n, (const float*)g_dv, (const float*)g_dx, (const float*)dvv,
+                                               (const float*)dxx, (const float*)dvx, (float*)grad_v, (float*)grad_x);
+  return check_launch("k_hess_vjp");
 }
 
 extern "C" const char* bessel_last_error(void) { return last_error(); }

@@ -34,7 +34,7 @@ def lib():
 def test_header_declares_the_paths():
     names = declared_functions()
     for required in ["bessel_logk", "bessel_logk_dv_dx", "bessel_range", "bessel_logk_backward",
-                     "bessel_last_error"]:
+                     "bessel_logk_hess", "bessel_hess_vjp", "bessel_last_error"]:
         assert required in names
 
 
@@ -124,3 +124,22 @@ def test_mlp_argument_errors(lib):
     assert lib.bessel_mlp_create(FAKE_A, 7, ctypes.byref(h)) == -1  # wrong parameter count
     assert lib.bessel_mlp_create(NULL, 4490, NULL) == -1
     assert lib.bessel_mlp_destroy(NULL) == 0
+
+
+def test_hess_argument_errors(lib):
+    outs = [FAKE_C, NULL, NULL, NULL, NULL, NULL]
+    assert lib.bessel_logk_hess(7, 4, FAKE_A, FAKE_B, *outs, 128, NULL) == -2
+    assert lib.bessel_logk_hess(1, -1, FAKE_A, FAKE_B, *outs, 128, NULL) == -1
+    assert lib.bessel_logk_hess(1, 4, FAKE_A, FAKE_B, *outs, 1, NULL) == -3
+    assert lib.bessel_logk_hess(1, 4, FAKE_A, FAKE_B, *([NULL] * 6), 128, NULL) == -1
+    assert lib.bessel_logk_hess(1, 4, FAKE_A, FAKE_B, FAKE_A, *([NULL] * 5), 128, NULL) == -6
+    assert lib.bessel_logk_hess(1, 4, FAKE_A, FAKE_B, FAKE_C, FAKE_C, *([NULL] * 4), 128, NULL) == -6
+    assert lib.bessel_logk_hess(1, 0, NULL, NULL, *([NULL] * 6), 128, NULL) == 0
+
+
+def test_hess_vjp_argument_errors(lib):
+    assert lib.bessel_hess_vjp(1, 4, NULL, NULL, FAKE_A, FAKE_A, FAKE_A, FAKE_B, NULL, NULL) == -1
+    assert lib.bessel_hess_vjp(1, 4, FAKE_A, NULL, FAKE_B, NULL, NULL, FAKE_C, NULL, NULL) == -1
+    assert lib.bessel_hess_vjp(1, 4, FAKE_A, NULL, FAKE_B, NULL, FAKE_B, FAKE_A, NULL, NULL) == -6
+    assert lib.bessel_hess_vjp(3, 4, FAKE_A, NULL, FAKE_B, NULL, FAKE_B, FAKE_C, NULL, NULL) == -2
+    assert lib.bessel_hess_vjp(1, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == 0
