@@ -258,6 +258,22 @@ def main():
     traffic = None
     if TRAFFIC["bytes_per_elem"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
         traffic = TRAFFIC["bytes_per_elem"] * args.n
+    # batch-size sweep in the paper's shape (Section 3.4: v = 10^{2r} - 1,
+    # x = 10^{3r' - 1}): microseconds per call, kernels and launch included
+    sweep = {"n": [], "f64_us": [], "f64_one_lane_us": [], "f32_mlp_us": []}
+    for n_s in (10, 100, 1000, 10000, 100000, 1000000):
+        vs_, xs_ = workloads.paper_sweep(n_s)
+        v64s, x64s = torch.tensor(vs_, device=dev), torch.tensor(xs_, device=dev)
+        v32s, x32s = v64s.float(), x64s.float()
+        reps = 200 if n_s <= 100000 else 20
+        sweep["n"].append(n_s)
+        sweep["f64_us"].append(1e3 * time_path(lambda: bk.logk(v64s, x64s, nbins=nb), reps, 5))
+        prev = bk.set_split_threshold(0)
+        sweep["f64_one_lane_us"].append(1e3 * time_path(lambda: bk.logk(v64s, x64s, nbins=nb), reps, 5))
+        bk.set_split_threshold(prev)
+        sweep["f32_mlp_us"].append(1e3 * time_path(lambda: bk.logk(v32s, x32s, nbins=nb, range="mlp", mlp=mlp),
+                                                   reps, 5))
+
     # the FP32 learned-range path against the plain FP64 method on the same batch
     speedup = {"fwd": paths["f32_mlp_fwd"]["evals_per_s"] / paths["f64_fwd"]["evals_per_s"],
                "fwd_bwd": paths["f32_mlp_fwd_bwd"]["evals_per_s"] / paths["f64_fwd_bwd"]["evals_per_s"]}
@@ -297,6 +313,7 @@ def main():
         "config": {"workload": "scale-2^24", "n": args.n, "nbins": nb, "range": "mlp", "seed": 1,
                    "path": "f32 learned-range fwd"},
         "speedup_vs_f64": speedup,
+        "batch_scaling": sweep,
         "err_vs_f64_path": err_f64,
         "paths": paths,
         "learned_range": mlp_info,

@@ -119,6 +119,22 @@ int bessel_logk_hess(int dtype, int64_t n, const void* v, const void* x, void* l
                      void* dxx, void* dvx, int nbins, void* hip_stream);
 
 /*
+ * bessel_set_split_threshold -- batch-size policy of bessel_logk and
+ * bessel_logk_dv_dx on the Newton bracket.  Batches of at most n elements run
+ * kernels that give each element 16 lanes (every lane finds the bracket, sums
+ * 1/16 of the bins, and the lanes add their FP64 partial sums): for small
+ * batches, where one lane per element would leave most of the GPU idle, this
+ * cuts the latency.  Larger batches run one lane per element.  The two
+ * layouts add the same terms in a different order, so results can differ in
+ * the last bits between them (both within the path's tolerance); for a given
+ * n and threshold they are deterministic.  n = 0 turns the split kernels off.
+ * Default 16384; at most BESSEL_MAX_SPLIT_THRESHOLD.  previous (nullable)
+ * receives the old value.  Process-wide; takes effect for later calls.
+ */
+#define BESSEL_MAX_SPLIT_THRESHOLD (1LL << 26)
+int bessel_set_split_threshold(int64_t n, int64_t* previous);
+
+/*
  * bessel_hess_vjp -- the backward step through (d/dv, d/dx) log K, with the
  * second derivatives a bessel_logk_hess call produced (the Hessian of log K is
  * symmetric):

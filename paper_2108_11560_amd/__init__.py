@@ -33,6 +33,7 @@ __all__ = [
     "logk",
     "logk_dv_dx",
     "logk_hess",
+    "set_split_threshold",
     "bessel_range",
     "log_bessel_k",
     "gh_logk_sum",
@@ -128,6 +129,14 @@ def logk_hess(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, want=(True,) *
                                   _stream_ptr(v.device))
     check(rc, "bessel_logk_hess")
     return tuple(outs)
+
+
+def set_split_threshold(n: int) -> int:
+    """Batches of at most n elements use the 16-lanes-per-element kernels
+    (latency of small batches); returns the previous threshold."""
+    prev = ctypes.c_int64()
+    check(load().bessel_set_split_threshold(int(n), ctypes.byref(prev)), "bessel_set_split_threshold")
+    return prev.value
 
 
 def bessel_range(v: torch.Tensor, x: torch.Tensor, range: str = "newton", mlp=None, want_fallback: bool = False):

@@ -39,6 +39,7 @@ SIGNATURES = {
     "bessel_logk_backward": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bessel_logk_hess": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "bessel_hess_vjp": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bessel_set_split_threshold": (_int, [_i64, _vp]),
     "bessel_mlp_create": (_int, [_vp, _i64, _vp]),
     "bessel_mlp_destroy": (_int, [_vp]),
     "bessel_mlp_set_params": (_int, [_vp, _vp, _i64]),

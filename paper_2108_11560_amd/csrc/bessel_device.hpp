@@ -532,4 +532,95 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   return s;
 }
 
+// ---------------------------------------------------------------------------
+// Bins of one sub-range, for kernels that split an element's nodes over
+// several lanes (small batches, where one lane per element would leave most
+// of the chip idle): nodes m in [m_lo, m_hi), and the last node m = nb when
+// with_end (then m_hi == nb).  The per-node arithmetic is that of bins_f32 /
+// bins_f64 with every recurrence started at m_lo; c_0 = c_nb = 1/2.
+// ---------------------------------------------------------------------------
+template <int DER>
+__device__ __forceinline__ BinSums sub_bins_f32(int nb, int m_lo, int m_hi, bool with_end, double v, double x,
+                                                double G, double t0, double t1) {
+  constexpr bool GRAD = DER >= 1;
+  const double h = (t1 - t0) / (double)nb;
+  const double vl = v * kLog2e;
+  const double xl = x * kLog2e;
+  const double Gl = (G + kLn2) * kLog2e;
+  const double dL = vl * h;
+  const double ta = fma((double)m_lo, h, t0);
+  const double eh = exp_f64(h);
+  const double ehi = rcp_f64(eh);
+  const double c2 = eh + ehi;
+  const double Ea = exp_f64(ta);
+  const double Eai = rcp_f64(Ea);
+  double Cp = 0.5 * (Ea * ehi + Eai * eh);
+  double C = 0.5 * (Ea + Eai);
+  const double Q = exp_f64(-2.0 * v * h);
+  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  double r = one_minus_exp_neg(2.0 * v * ta);
+  double u = 2.0 - r;
+  double L = fma((double)m_lo, dL, fma(vl, t0, -Gl));
+  BinSums s{};
+  for (int m = m_lo; m <= m_hi; ++m) {
+    if (m == m_hi) {
+      if (!with_end) break;
+      L = fma(vl, t1, -Gl);
+    }
+    float w = hexp2((float)fma(-xl, C, L));
+    if (m == 0 || m == nb) w *= 0.5f;
+    const double wd = (double)w;
+    s.S0 = fma(wd, u, s.S0);
+    if (GRAD) {
+      const double t = (m == nb) ? t1 : fma((double)m, h, t0);
+      s.Sv = fma(wd * r, t, s.Sv);
+      s.Sx = fma(wd * u, C, s.Sx);
+      r = fma(r, Q, E2);
+    }
+    u = fma(u, Q, E2);
+    L += dL;
+    const double Cn = fma(c2, C, -Cp);
+    Cp = C;
+    C = Cn;
+  }
+  return s;
+}
+
+template <int DER>
+__device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool with_end, double v, double x,
+                                                double G, double t0, double t1) {
+  constexpr bool GRAD = DER >= 1;
+  const double h = (t1 - t0) / (double)nb;
+  const double Gs = G + kLn2;
+  const double xh = 0.5 * x;
+  const double eh = exp_f64(h), ehi = rcp_f64(eh);
+  const double Q = exp_f64(-2.0 * v * h);
+  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  double r = one_minus_exp_neg(2.0 * v * fma((double)m_lo, h, t0));
+  double u = 2.0 - r;
+  double E = 0.0, Ei = 0.0;
+  BinSums s{};
+  for (int m = m_lo; m <= m_hi; ++m) {
+    if (m == m_hi && !with_end) break;
+    const double t = (m == nb) ? t1 : fma((double)m, h, t0);
+    if ((m - m_lo) % kChunk == 0 || m == nb) {  // products re-anchored every kChunk nodes
+      E = exp_f64(t);
+      Ei = rcp_f64(E);
+    }
+    const double ch2 = E + Ei;
+    double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    if (m == 0 || m == nb) w *= 0.5;
+    s.S0 = fma(w, u, s.S0);
+    if (GRAD) {
+      s.Sv = fma(w * r, t, s.Sv);
+      s.Sx = fma(w * u, 0.5 * ch2, s.Sx);
+      r = fma(r, Q, E2);
+    }
+    u = fma(u, Q, E2);
+    E *= eh;
+    Ei *= ehi;
+  }
+  return s;
+}
+
 }  // namespace bk

@@ -11,6 +11,9 @@
 namespace bk {
 
 constexpr int kBlock = 256;  // 4 wave64 per workgroup
+// Batches of at most this many elements take the kernels that split each
+// element's nodes over 16 lanes (log K and first derivatives, Newton bracket).
+constexpr int64_t kDefaultSplitThreshold = 16384;
 
 int set_error(int code, const char* fmt, ...);
 const char* last_error();

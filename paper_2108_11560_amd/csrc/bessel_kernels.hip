@@ -7,6 +7,7 @@
 // divisions is what makes the time per element uniform).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
 #include <cstdarg>
 #include <cstdint>
@@ -115,6 +116,70 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
   if (dvx) dvx[i] = (T)lvx;
 }
 
+// Small batches: kSplit lanes per element.  Every lane of an element's group
+// finds the same bracket (the search is short and deterministic, so nothing
+// is broadcast), integrates 1/kSplit of the nodes, and the group adds its
+// FP64 partial sums with butterfly shuffles; lane 0 of the group writes.
+// Lanes past n work on a dummy element so that every lane reaches the shuffles.
+constexpr int kSplit = 16;
+
+__device__ __forceinline__ double group_sum(double a) {
+#pragma unroll
+  for (int m = kSplit / 2; m >= 1; m >>= 1) a += __shfl_xor(a, m);
+  return a;
+}
+
+template <typename T, int NB, bool GRAD>
+__global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, const T* __restrict__ vin,
+                                                       const T* __restrict__ xin, const T* __restrict__ gout,
+                                                       T* __restrict__ logk, T* __restrict__ dv,
+                                                       T* __restrict__ dx) {
+  const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kSplit;
+  const int k = (int)(threadIdx.x % kSplit);
+  const bool in = e < n;
+  const int nb = NB > 0 ? NB : nbins;
+  const double vs = in ? (double)vin[e] : 1.0;
+  const double x = in ? (double)xin[e] : 1.0;
+  double lk, dvv, dxv;
+  const bool special = domain_special(vs, x, lk, dvv, dxv);
+  const double v = fabs(vs);
+  BinSums s{};
+  Bracket b{};
+  if (!special) {
+    b = find_bracket(v, x, margin_of<T>());
+    const int m_lo = (k * nb) / kSplit, m_hi = ((k + 1) * nb) / kSplit;
+    if constexpr (sizeof(T) == 8)
+      s = sub_bins_f64<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.G, (double)b.t0, (double)b.t1);
+    else
+      s = sub_bins_f32<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.G, (double)b.t0, (double)b.t1);
+  }
+  const double S0 = group_sum(s.S0);
+  const double Sv = GRAD ? group_sum(s.Sv) : 0.0;
+  const double Sx = GRAD ? group_sum(s.Sx) : 0.0;
+  if (!in || k != 0) return;
+  if (!special) {
+    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+    const double rS0 = rcp_f64(S0);
+    lk = b.G + log_f64(h * S0);
+    if (GRAD) {
+      dvv = (v == 0.0) ? 0.0 : copysign(Sv * rS0, vs);
+      dxv = -Sx * rS0;
+    }
+  }
+  if (GRAD) {
+    if (gout) {
+      const double go = (double)gout[e];
+      dvv *= go;
+      dxv *= go;
+    }
+    dv[e] = (T)dvv;
+    dx[e] = (T)dxv;
+    if (logk) logk[e] = (T)lk;
+  } else {
+    logk[e] = (T)lk;
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_range(int64_t n, const T* __restrict__ vin, const T* __restrict__ xin,
                                                   T* __restrict__ t0, T* __restrict__ t1, T* __restrict__ tp,
@@ -202,9 +267,22 @@ int grid_for(int64_t n, dim3& grid) {
   return BESSEL_OK;
 }
 
+// Batches of at most this many elements run kSplit lanes per element.
+static std::atomic<int64_t> g_split_threshold{kDefaultSplitThreshold};
+
 template <typename T, bool GRAD>
 static void launch_logk(dim3 grid, hipStream_t st, int64_t n, int nbins, const T* v, const T* x, const T* go, T* lk,
                         T* dv, T* dx) {
+  if (n <= g_split_threshold.load(std::memory_order_relaxed)) {
+    const dim3 sgrid((unsigned)((n * kSplit + kBlock - 1) / kBlock));
+    switch (nbins) {
+      case 64: k_logk_split<T, 64, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+      case 128: k_logk_split<T, 128, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+      case 256: k_logk_split<T, 256, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+      default: k_logk_split<T, 0, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+    }
+    return;
+  }
   switch (nbins) {
     case 64: k_logk<T, 64, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
     case 128: k_logk<T, 128, GRAD><<<grid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
@@ -433,6 +511,15 @@ extern "C" int bessel_hess_vjp(int dtype, int64_t n, const void* g_dv, const voi
     k_hess_vjp<float><<<grid, kBlock, 0, st>>>(n, (const float*)g_dv, (const float*)g_dx, (const float*)dvv,
                                                (const float*)dxx, (const float*)dvx, (float*)grad_v, (float*)grad_x);
   return check_launch("k_hess_vjp");
+}
+
+extern "C" int bessel_set_split_threshold(int64_t n, int64_t* previous) {
+  if (n < 0) return set_error(BESSEL_ERR_ARG, "threshold %lld < 0", (long long)n);
+  if (n > BESSEL_MAX_SPLIT_THRESHOLD)
+    return set_error(BESSEL_ERR_ARG, "threshold %lld above %lld", (long long)n, (long long)BESSEL_MAX_SPLIT_THRESHOLD);
+  const int64_t old = g_split_threshold.exchange(n);
+  if (previous) *previous = old;
+  return BESSEL_OK;
 }
 
 extern "C" const char* bessel_last_error(void) { return last_error(); }

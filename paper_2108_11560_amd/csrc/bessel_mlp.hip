@@ -210,8 +210,17 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce(const float* __restrict__
                                                        float* __restrict__ grad, float* __restrict__ loss) {
   const int e = blockIdx.x * kBlock + threadIdx.x;
   if (e > kNW) return;
+  // blocks in order (deterministic); eight loads in flight per group
   double acc = 0.0;
-  for (int b = 0; b < nblocks; ++b) acc += (double)partial[(int64_t)b * (kNW + 1) + e];
+  int b = 0;
+  for (; b + 8 <= nblocks; b += 8) {
+    float p[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) p[j] = partial[(int64_t)(b + j) * (kNW + 1) + e];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc += (double)p[j];
+  }
+  for (; b < nblocks; ++b) acc += (double)partial[(int64_t)b * (kNW + 1) + e];
   if (e < kNW) grad[e] = (float)acc;
   else if (loss) *loss = (float)acc;
 }
@@ -272,11 +281,14 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 //           k-block and lane, columns in the order the layer-1 results reach
 //           the lane
 //   B2      2 log2(e) (b2 + sum_j W2[., j]) in accumulator order
-//   W3      -2 W3 in accumulator order;  b3' = b3 + sum_i W3[., i]
+//   A3      layer-3 fragments (bf16 of -2 W3) per element tile et and
+//           k-block: output c on row 4 et + c, zero rows elsewhere, so that
+//           the four tiles share one accumulator and each lane ends with the
+//           outputs of its own element;  b3' = b3 + sum_i W3[., i]
 // With s = 1 / (1 + 2^{a'}), a' = 2 log2(e) a, tanh(a) = 1 - 2 s, so each layer
 // takes the s of the one before:  W h + b = (b + sum W) - 2 W s.
-constexpr int qHdr = 0, qA1 = 16, qA2 = qA1 + 4 * 16 * 4, qB2 = qA2 + 4 * 2 * 64 * 4, qW3 = qB2 + kH,
-              kNQ = qW3 + 2 * kH;
+constexpr int qHdr = 0, qA1 = 16, qA2 = qA1 + 4 * 16 * 4, qB2 = qA2 + 4 * 2 * 64 * 4, qA3 = qB2 + kH,
+              kNQ = qA3 + 4 * 2 * 64 * 4;
 
 // hidden unit fed by k-slot j of lane group g in k-block kb of layer 2: the
 // layer-1 accumulators of tiles 2kb and 2kb+1 hold rows 4g..4g+3 of each
@@ -299,13 +311,15 @@ __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ P
     double rs = (double)P[ob2 + h];
     for (int j = 0; j < kH; ++j) rs += (double)P[oW2 + h * kH + j];
     Q[qB2 + h] = k2Log2e * (float)rs;  // 16 ho + 4 g + r is the natural order
-    Q[qW3 + h] = -2.0f * P[oW3 + h];
-    Q[qW3 + kH + h] = -2.0f * P[oW3 + kH + h];
   }
+  __bf16* a3 = reinterpret_cast<__bf16*>(Q + qA3);
   for (int idx = t; idx < 4 * 2 * 64 * 8; idx += kBlock) {
-    const int j = idx & 7, l = (idx >> 3) & 63, kb = (idx >> 9) & 1, ho = idx >> 10;
-    const int row = 16 * ho + (l & 15);
+    const int j = idx & 7, l = (idx >> 3) & 63, kb = (idx >> 9) & 1, hi = idx >> 10;
+    const int row = 16 * hi + (l & 15);
     a2[idx] = (__bf16)(-2.0f * k2Log2e * P[oW2 + row * kH + l2_col(kb, l >> 4, j)]);
+    // layer 3 for element tile et = hi: output c on row 4 et + c
+    const int c = (l & 15) - 4 * hi;
+    a3[idx] = (c == 0 || c == 1) ? (__bf16)(-2.0f * P[oW3 + c * kH + l2_col(kb, l >> 4, j)]) : (__bf16)0.0f;
   }
   if (t < 2) {
     double s = (double)P[ob3 + t];
@@ -337,7 +351,9 @@ __device__ __forceinline__ void mlp_features_q(const float* __restrict__ Q, floa
 // features only from lane group et (its own elements), zeros elsewhere.
 // Layer 2: D[hidden out][element] = A2 * S1^T + B2; the layer-1 accumulators
 // of a lane are already its B fragments (k-slots permuted as l2_col).
-// Layer 3 on the VALU in FP32, finished by sums over the four lane groups.
+// Layer 3: D[4 et + c][element] += A3(et) * S2^T over the four element tiles
+// into one accumulator; lane l = 16 g + e ends with rows 4g, 4g + 1 of column
+// e, the two outputs of its own element.
 // Every lane of the wavefront must call it.
 __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float z0, float z1, float& y0, float& y1) {
   const int l = threadIdx.x & 63;
@@ -361,8 +377,8 @@ __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float
   for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
   const bf16x8* A1 = reinterpret_cast<const bf16x8*>(Q + qA1);
   const bf16x8* A2 = reinterpret_cast<const bf16x8*>(Q + qA2);
-  bf16x8 a1[4], a2[4][2];
-  f32x4 b2[4], w3a[4], w3b[4];
+  bf16x8 a1[4], a2[4][2], a3[4][2];
+  f32x4 b2[4];
 #pragma unroll
   for (int ht = 0; ht < 4; ++ht) a1[ht] = A1[ht * 16 + lr];
 #pragma unroll
@@ -370,10 +386,11 @@ __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float
     a2[ho][0] = A2[(ho * 2 + 0) * 64 + l];
     a2[ho][1] = A2[(ho * 2 + 1) * 64 + l];
     b2[ho] = *reinterpret_cast<const f32x4*>(Q + qB2 + 16 * ho + 4 * lg);
-    w3a[ho] = *reinterpret_cast<const f32x4*>(Q + qW3 + 16 * ho + 4 * lg);
-    w3b[ho] = *reinterpret_cast<const f32x4*>(Q + qW3 + kH + 16 * ho + 4 * lg);
+    const bf16x8* A3 = reinterpret_cast<const bf16x8*>(Q + qA3);
+    a3[ho][0] = A3[(ho * 2 + 0) * 64 + l];  // ho doubles as the element tile here
+    a3[ho][1] = A3[(ho * 2 + 1) * 64 + l];
   }
-  float p0[4], p1[4];
+  f32x4 acc = {Q[qHdr + 6], Q[qHdr + 7], 0.0f, 0.0f};  // rows 4g + c start at b3'[c]
 #pragma unroll
   for (int et = 0; et < 4; ++et) {
     const bf16x8 bz = (lg == et) ? zf : zero;
@@ -385,28 +402,19 @@ __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float
 #pragma unroll
       for (int r = 0; r < 4; ++r) h[ht >> 1][4 * (ht & 1) + r] = (__bf16)hrcp(1.0f + hexp2(d[r]));
     }
-    float s0 = 0.0f, s1 = 0.0f;
+    bf16x8 h3[2];
 #pragma unroll
     for (int ho = 0; ho < 4; ++ho) {
       f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][0], h[0], b2[ho], 0, 0, 0);
       d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][1], h[1], d, 0, 0, 0);
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const float sg = hrcp(1.0f + hexp2(d[r]));
-        s0 = fmaf(w3a[ho][r], sg, s0);
-        s1 = fmaf(w3b[ho][r], sg, s1);
-      }
+      for (int r = 0; r < 4; ++r) h3[ho >> 1][4 * (ho & 1) + r] = (__bf16)hrcp(1.0f + hexp2(d[r]));
     }
-    s0 += __shfl_xor(s0, 16);
-    s1 += __shfl_xor(s1, 16);
-    s0 += __shfl_xor(s0, 32);
-    s1 += __shfl_xor(s1, 32);
-    p0[et] = s0;
-    p1[et] = s1;
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[et][0], h3[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[et][1], h3[1], acc, 0, 0, 0);
   }
-  // lane l = 16 lg + lr owns element-tile lg
-  y0 = Q[qHdr + 6] + (lg == 0 ? p0[0] : lg == 1 ? p0[1] : lg == 2 ? p0[2] : p0[3]);
-  y1 = Q[qHdr + 7] + (lg == 0 ? p1[0] : lg == 1 ? p1[1] : lg == 2 ? p1[2] : p1[3]);
+  y0 = acc[0];
+  y1 = acc[1];
 }
 
 __global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __restrict__ Q, int64_t n,

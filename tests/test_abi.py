@@ -143,3 +143,13 @@ def test_hess_vjp_argument_errors(lib):
     assert lib.bessel_hess_vjp(1, 4, FAKE_A, NULL, FAKE_B, NULL, FAKE_B, FAKE_A, NULL, NULL) == -6
     assert lib.bessel_hess_vjp(3, 4, FAKE_A, NULL, FAKE_B, NULL, FAKE_B, FAKE_C, NULL, NULL) == -2
     assert lib.bessel_hess_vjp(1, 0, NULL, NULL, NULL, NULL, NULL, NULL, NULL, NULL) == 0
+
+
+def test_split_threshold_setter(lib):
+    prev = ctypes.c_int64()
+    assert lib.bessel_set_split_threshold(-1, ctypes.byref(prev)) == -1
+    assert lib.bessel_set_split_threshold((1 << 26) + 1, NULL) == -1
+    assert lib.bessel_set_split_threshold(77, ctypes.byref(prev)) == 0
+    old = prev.value
+    assert lib.bessel_set_split_threshold(old, ctypes.byref(prev)) == 0
+    assert prev.value == 77

@@ -169,8 +169,14 @@ def test_forced_fallback_is_bitwise_newton(mods):
     bk, M = mods
     v, x, _ = workloads.scale_pairs(5000, seed=404)
     vt, xt = dev32(v), dev32(x)
-    newton = bk.logk(vt, xt, nbins=128)
-    nl, ndv, ndx = bk.logk_dv_dx(vt, xt, nbins=128)
+    # the fallback kernel runs one lane per element: compare with the Newton
+    # path in that layout (small batches otherwise take the 16-lane kernels)
+    prev = bk.set_split_threshold(0)
+    try:
+        newton = bk.logk(vt, xt, nbins=128)
+        nl, ndv, ndx = bk.logk_dv_dx(vt, xt, nbins=128)
+    finally:
+        bk.set_split_threshold(prev)
     # zero weights with a large negative t1 margin: t1 = e^{-30}, every check fails
     p = np.zeros(M.NPARAMS, dtype=np.float32)
     p[M.O_META:M.O_META + 6] = [1.0, 3.0, 0.0, 4.0, -30.0, 0.0]
