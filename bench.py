@@ -123,6 +123,31 @@ def time_path(fn, steps, warmup):
     return start.elapsed_time(end) / steps  # ms per step
 
 
+def graph_us_per_call(fn, calls: int = 50, replays: int = 20):
+    """Microseconds per call when `calls` calls are captured in one HIP graph
+    and the graph is replayed: the device-side cost without the per-call host
+    launch overhead."""
+    import torch
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        fn()
+    torch.cuda.current_stream().wait_stream(s)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        for _ in range(calls):
+            fn()
+    g.replay()
+    torch.cuda.synchronize()
+    start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    start.record()
+    for _ in range(replays):
+        g.replay()
+    end.record()
+    torch.cuda.synchronize()
+    return 1e3 * start.elapsed_time(end) / (replays * calls)
+
+
 def cpu_baseline(v, x, v32, x32, gpu, budget_s):
     """The oracle (as it stands) on a bounded random sample, on the host cores.
 
@@ -259,8 +284,10 @@ def main():
     if TRAFFIC["bytes_per_elem"] and TRAFFIC["sources_sha256"] == kernel_sources_sha256():
         traffic = TRAFFIC["bytes_per_elem"] * args.n
     # batch-size sweep in the paper's shape (Section 3.4: v = 10^{2r} - 1,
-    # x = 10^{3r' - 1}): microseconds per call, kernels and launch included
-    sweep = {"n": [], "f64_us": [], "f64_one_lane_us": [], "f32_mlp_us": []}
+    # x = 10^{3r' - 1}): microseconds per call, kernels and launch included;
+    # f64_graph_us replays 50 captured calls per launch (device-side cost)
+    sweep = {"n": [], "f64_us": [], "f64_one_lane_us": [], "f64_graph_us": [], "f64_one_lane_graph_us": [],
+             "f32_mlp_us": []}
     for n_s in (10, 100, 1000, 10000, 100000, 1000000):
         vs_, xs_ = workloads.paper_sweep(n_s)
         v64s, x64s = torch.tensor(vs_, device=dev), torch.tensor(xs_, device=dev)
@@ -268,8 +295,10 @@ def main():
         reps = 200 if n_s <= 100000 else 20
         sweep["n"].append(n_s)
         sweep["f64_us"].append(1e3 * time_path(lambda: bk.logk(v64s, x64s, nbins=nb), reps, 5))
+        sweep["f64_graph_us"].append(graph_us_per_call(lambda: bk.logk(v64s, x64s, nbins=nb)))
         prev = bk.set_split_threshold(0)
         sweep["f64_one_lane_us"].append(1e3 * time_path(lambda: bk.logk(v64s, x64s, nbins=nb), reps, 5))
+        sweep["f64_one_lane_graph_us"].append(graph_us_per_call(lambda: bk.logk(v64s, x64s, nbins=nb)))
         bk.set_split_threshold(prev)
         sweep["f32_mlp_us"].append(1e3 * time_path(lambda: bk.logk(v32s, x32s, nbins=nb, range="mlp", mlp=mlp),
                                                    reps, 5))

@@ -22,6 +22,7 @@ computation runs in the library's kernels.
 
 from __future__ import annotations
 
+import contextlib
 import ctypes
 
 import torch
@@ -69,6 +70,14 @@ def _check_pair(v: torch.Tensor, x: torch.Tensor):
     return v.contiguous(), x.contiguous()
 
 
+def _on(device: torch.device):
+    """The device context for a call, skipped when it is already current (a
+    per-call cost that dominates small batches)."""
+    if device.index is None or device.index == torch.cuda.current_device():
+        return contextlib.nullcontext()
+    return torch.cuda.device(device)
+
+
 def _ptr(t: torch.Tensor | None):
     return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
 
@@ -92,7 +101,7 @@ def logk(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, range: str = "newto
     v, x = _check_pair(v, x)
     out = torch.empty_like(v)
     lib = load()
-    with torch.cuda.device(v.device):
+    with _on(v.device):
         rc = lib.bessel_logk(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), _ptr(out), int(nbins),
                              _range_code(range), _mlp_ptr(mlp), _stream_ptr(v.device))
     check(rc, "bessel_logk")
@@ -111,7 +120,7 @@ def logk_dv_dx(v: torch.Tensor, x: torch.Tensor, grad_out: torch.Tensor | None =
     dv = torch.empty_like(v)
     dx = torch.empty_like(v)
     lib = load()
-    with torch.cuda.device(v.device):
+    with _on(v.device):
         rc = lib.bessel_logk_dv_dx(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), _ptr(grad_out), _ptr(lk), _ptr(dv),
                                    _ptr(dx), int(nbins), _range_code(range), _mlp_ptr(mlp), _stream_ptr(v.device))
     check(rc, "bessel_logk_dv_dx")
@@ -124,7 +133,7 @@ def logk_hess(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, want=(True,) *
     v, x = _check_pair(v, x)
     outs = [torch.empty_like(v) if w else None for w in want]
     lib = load()
-    with torch.cuda.device(v.device):
+    with _on(v.device):
         rc = lib.bessel_logk_hess(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), *(_ptr(o) for o in outs), int(nbins),
                                   _stream_ptr(v.device))
     check(rc, "bessel_logk_hess")
@@ -145,7 +154,7 @@ def bessel_range(v: torch.Tensor, x: torch.Tensor, range: str = "newton", mlp=No
     t0, t1, tp, gp = torch.empty_like(v), torch.empty_like(v), torch.empty_like(v), torch.empty_like(v)
     fb = torch.empty(v.shape, dtype=torch.uint8, device=v.device) if want_fallback else None
     lib = load()
-    with torch.cuda.device(v.device):
+    with _on(v.device):
         rc = lib.bessel_range(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), _ptr(t0), _ptr(t1), _ptr(tp), _ptr(gp),
                               _range_code(range), _mlp_ptr(mlp), _ptr(fb), _stream_ptr(v.device))
     check(rc, "bessel_range")
@@ -169,7 +178,7 @@ def gh_logk_sum(lam: torch.Tensor, alpha: torch.Tensor, delta: torch.Tensor, mu:
     grads = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)] if want_grad else [None] * 4
     gs = grad_sum.contiguous() if grad_sum is not None else None
     lib = load()
-    with torch.cuda.device(dev):
+    with _on(dev):
         rc = lib.bessel_gh_logk_sum(n, *(_ptr(t) for t in sets), y.numel(), _ptr(y), _ptr(gs), _ptr(out),
                                     *(_ptr(g) for g in grads), int(nbins), RANGE_NEWTON, ctypes.c_void_p(0),
                                     _stream_ptr(dev))
@@ -202,7 +211,7 @@ class _BesselDLogK(torch.autograd.Function):
             return (torch.zeros_like(dvv) if gv is not None else None,
                     torch.zeros_like(dvv) if gx is not None else None, None)
         lib = load()
-        with torch.cuda.device(dvv.device):
+        with _on(dvv.device):
             rc = lib.bessel_hess_vjp(_dtype_code(dvv), dvv.numel(), _ptr(g_dv), _ptr(g_dx), _ptr(dvv), _ptr(dxx),
                                      _ptr(dvx), _ptr(gv), _ptr(gx), _stream_ptr(dvv.device))
         check(rc, "bessel_hess_vjp")
@@ -244,7 +253,7 @@ class BesselLogK(torch.autograd.Function):
         gv = torch.empty_like(dv) if ctx.needs_input_grad[0] else None
         gx = torch.empty_like(dx) if ctx.needs_input_grad[1] else None
         lib = load()
-        with torch.cuda.device(dv.device):
+        with _on(dv.device):
             rc = lib.bessel_logk_backward(_dtype_code(dv), dv.numel(), _ptr(go), _ptr(dv), _ptr(dx), _ptr(gv),
                                           _ptr(gx), _stream_ptr(dv.device))
         check(rc, "bessel_logk_backward")

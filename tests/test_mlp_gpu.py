@@ -120,8 +120,10 @@ def test_training_reduces_loss(mods):
 @pytest.fixture(scope="module")
 def trained(mods):
     bk, M = mods
+    # trained and calibrated as the benchmark does: 2^20 samples (seed 4),
+    # 20 000 Adam steps, margins on 2^16 held-out pairs (seed 8)
     mlp = M.RangeMLP(M.glorot_params(0))
-    v, x, _ = workloads.scale_pairs(1 << 18, seed=4)
+    v, x, _ = workloads.scale_pairs(1 << 20, seed=4)
     mlp.train(dev32(v), dev32(x), steps=20000, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
     vc, xc, _ = workloads.scale_pairs(1 << 16, seed=8)
     m1, m0, rate = M.calibrate_margins(mlp, dev32(vc), dev32(xc), target_fallback=0.005)
@@ -146,6 +148,33 @@ def test_learned_range_parity(mods, trained, nbins):
     _, rdv, rdx = oracle.logk(host(vt)[idx], host(xt)[idx], deriv=True)
     assert (np.abs(host(dv)[idx] - rdv) / np.maximum(1.0, np.abs(rdv))).max() <= 1e-5
     assert (np.abs(host(dx)[idx] - rdx) / np.maximum(1.0, np.abs(rdx))).max() <= 1e-5
+
+
+def test_learned_range_full_size(mods, trained):
+    """The benchmark's configuration: 2^24 scale pairs, FP32, 128 bins, forward
+    and forward+backward; the oracle checks a stratified sample, the FP64 path
+    (at the FP32-rounded inputs) every element."""
+    bk, M = mods
+    mlp, _ = trained
+    v, x, strata = workloads.scale_pairs(1 << 24, seed=1)
+    idx = workloads.stratified_subset(strata, 1 << 13, seed=11)
+    vt, xt = dev32(v), dev32(x)
+    idx_t = torch.tensor(idx, device="cuda")
+    lk = bk.logk(vt, xt, nbins=128, range="mlp", mlp=mlp)
+    assert mlp.fallback_count() <= 0.02 * v.size
+    assert bool(torch.isfinite(lk).all())
+    ref = oracle.logk(host(vt[idx_t]), host(xt[idx_t]))
+    assert (np.abs(host(lk[idx_t]) - ref) / np.maximum(1.0, np.abs(ref))).max() <= 1e-5
+    ref64 = bk.logk(vt.double(), xt.double(), nbins=128)
+    assert float(((lk.double() - ref64).abs() / ref64.abs().clamp_min(1.0)).max()) <= 1e-5
+    del ref64
+    go = dev32(workloads.upstream_grad(v.size, seed=13))
+    l2, dv, dx = bk.logk_dv_dx(vt, xt, grad_out=go, nbins=128, range="mlp", mlp=mlp)
+    assert torch.equal(l2, lk)
+    _, rdv, rdx = oracle.logk(host(vt[idx_t]), host(xt[idx_t]), deriv=True)
+    g = host(go[idx_t])
+    assert (np.abs(host(dv[idx_t]) - g * rdv) / np.maximum(1.0, np.abs(g * rdv))).max() <= 1e-5
+    assert (np.abs(host(dx[idx_t]) - g * rdx) / np.maximum(1.0, np.abs(g * rdx))).max() <= 1e-5
 
 
 def test_learned_brackets_contain_exact_set(mods, trained):
