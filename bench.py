@@ -64,9 +64,9 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the kernel sources whose
 # hash is recorded here; reported only while the sources still match.
-TRAFFIC = {"sources_sha256": "47e2cc485e7d4c41d02bdde18171a3bc57b454d958422d2bc288e4f49180139f",
-           # fused (65657 * 2 + 67947 KiB) + fallback (7494 * 2 + 1905 KiB) per 2^24 elements
-           "bytes_per_elem": 13.193}
+TRAFFIC = {"sources_sha256": "7e6df30867f8931da14acb122f905613029138d08259e1aba070d28494ccd86a",
+           # fused (65679 * 2 + 65800 KiB) + fallback (737 * 2 + 168 KiB) per 2^24 elements
+           "bytes_per_elem": 12.134}
 
 
 def kernel_sources_sha256() -> str:
@@ -102,6 +102,7 @@ def parse():
     p.add_argument("--mlp-steps", type=int, default=20000)
     p.add_argument("--copy-check", action="store_true",
                    help="also run a plain 256 MiB device copy (calibrates the FETCH_SIZE / WRITE_SIZE counters)")
+    p.add_argument("--no-sweep", action="store_true", help="skip the batch-size sweep")
     p.add_argument("--save-mlp", default=None, help="write the trained, calibrated predictor (.npy)")
     p.add_argument("--load-mlp", default=None,
                    help="use a predictor saved by --save-mlp instead of training one (for counter runs, "
@@ -288,7 +289,7 @@ def main():
     # f64_graph_us replays 50 captured calls per launch (device-side cost)
     sweep = {"n": [], "f64_us": [], "f64_one_lane_us": [], "f64_graph_us": [], "f64_one_lane_graph_us": [],
              "f32_mlp_us": []}
-    for n_s in (10, 100, 1000, 10000, 100000, 1000000):
+    for n_s in () if args.no_sweep else (10, 100, 1000, 10000, 100000, 1000000):
         vs_, xs_ = workloads.paper_sweep(n_s)
         v64s, x64s = torch.tensor(vs_, device=dev), torch.tensor(xs_, device=dev)
         v32s, x32s = v64s.float(), x64s.float()

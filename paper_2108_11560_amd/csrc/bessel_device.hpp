@@ -204,6 +204,21 @@ __device__ __forceinline__ bool domain_special(double v, double x, double& logk,
   return false;
 }
 
+// Final step of a path in the precision of its output: log(h S0) and 1/S0.
+// FP32 outputs take the hardware log2 and reciprocal (errors of ~1 ulp of
+// FP32, far below the FP32 bar); FP64 outputs the FP64 routines above.
+template <bool F64>
+__device__ __forceinline__ double log_of(double y) {
+  if constexpr (F64) return log_f64(y);
+  else return (double)(kLn2F * hlog2((float)y));
+}
+
+template <bool F64>
+__device__ __forceinline__ double rcp_of(double y) {
+  if constexpr (F64) return rcp_f64(y);
+  else return (double)hrcp((float)y);
+}
+
 // ---------------------------------------------------------------------------
 // Bracket (Sections 2.1-2.3), redesigned for fixed trip counts so a wavefront
 // never waits on a slow lane.  All loops below have compile-time trip counts.

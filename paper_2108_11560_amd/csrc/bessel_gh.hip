@@ -54,8 +54,8 @@ __global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nc
       const Bracket b = find_bracket(v, x, kMarginGh);
       const BinSums s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
       const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-      const double rS0 = rcp_f64(s.S0);
-      lk = b.G + log_f64(h * s.S0);
+      const double rS0 = rcp_of<false>(s.S0);
+      lk = b.G + log_of<false>(h * s.S0);
       dv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
       dx = -s.Sx * rS0;
     }

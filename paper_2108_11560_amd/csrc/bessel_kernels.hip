@@ -55,9 +55,10 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
     const Bracket b = find_bracket(v, x, margin_of<T>());
     const BinSums s = run_bins<T, GRAD ? 1 : 0>(nb, v, x, b);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-    const double rS0 = rcp_f64(s.S0);
-    lk = b.G + log_f64(h * s.S0);
+    constexpr bool F64 = sizeof(T) == 8;
+    lk = b.G + log_of<F64>(h * s.S0);
     if (GRAD) {
+      const double rS0 = rcp_of<F64>(s.S0);
       dvv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
       dxv = -s.Sx * rS0;
     }
@@ -98,11 +99,15 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
     const Bracket b = find_bracket(v, x, margin_of<T>());
     const BinSums s = run_bins<T, 2>(nb, v, x, b);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+    constexpr bool F64 = sizeof(T) == 8;
+    // first order as bessel_logk_dv_dx (same operations, same results); the
+    // variances below lose digits to cancellation, so they take FP64 1/S0
+    const double rS0o = rcp_of<F64>(s.S0);
+    lk = b.G + log_of<F64>(h * s.S0);
+    lv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0o, vs);
+    lx = -s.Sx * rS0o;
     const double rS0 = rcp_f64(s.S0);
     const double ev = s.Sv * rS0, ex = s.Sx * rS0;
-    lk = b.G + log_f64(h * s.S0);
-    lv = (v == 0.0) ? 0.0 : copysign(ev, vs);
-    lx = -ex;
     lvv = fma(-ev, ev, s.Svv * rS0);
     lxx = fma(-ex, ex, s.Sxx * rS0);
     const double mvx = fma(ev, ex, -s.Svx * rS0);  // any sign: flip it for v < 0, do not replace it
@@ -159,9 +164,10 @@ __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, con
   if (!in || k != 0) return;
   if (!special) {
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-    const double rS0 = rcp_f64(S0);
-    lk = b.G + log_f64(h * S0);
+    constexpr bool F64 = sizeof(T) == 8;
+    lk = b.G + log_of<F64>(h * S0);
     if (GRAD) {
+      const double rS0 = rcp_of<F64>(S0);
       dvv = (v == 0.0) ? 0.0 : copysign(Sv * rS0, vs);
       dxv = -Sx * rS0;
     }

@@ -493,8 +493,8 @@ __global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q
       ok = accept_bins(s, t0);
       if (ok) {
         const double h = ((double)t1 - (double)t0) / (double)nb;
-        const double rS0 = rcp_f64(s.S0);
-        lk = (double)G + log_f64(h * s.S0);
+        const double rS0 = rcp_of<false>(s.S0);
+        lk = (double)G + log_of<false>(h * s.S0);
         if (GRAD) {
           dvv = (v == 0.0f) ? 0.0 : copysign(s.Sv * rS0, (double)vs);
           dxv = -s.Sx * rS0;
@@ -560,8 +560,8 @@ __global__ __launch_bounds__(kBlock) void k_logk_fallback(int nbins, const int* 
     }
     const BinSums s = bins_f32<GRAD>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-    const double rS0 = rcp_f64(s.S0);
-    if (logk) logk[i] = (float)(b.G + log_f64(h * s.S0));
+    const double rS0 = rcp_of<false>(s.S0);
+    if (logk) logk[i] = (float)(b.G + log_of<false>(h * s.S0));
     if (GRAD) {
       double dvv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
       double dxv = -s.Sx * rS0;
