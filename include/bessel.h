@@ -29,6 +29,14 @@
  *     x == +inf -> log K = -inf;  |v| == inf with finite x > 0 -> log K = +inf;
  *     derivatives are NaN in all of these.  v < 0 is evaluated at |v|
  *     (K_{-v} = K_v) with d/dv negated; v == 0 gives d/dv == 0 exactly.
+ *     0 < x < 1e-36 -> NaN as well: below the range of the bracket search
+ *     (which runs in FP32).
+ *   - Validated domain (tests against the CPU oracle at the default 128 bins):
+ *     |v| <= 1e3 with 1e-6 <= x <= 1e5 at the F64 bar (mixed error 1e-12) and
+ *     1e-35 <= x <= 1e5 at the F32 bar (1e-5).  Outside it the results stay
+ *     finite but lose accuracy: below x ~ 1e-6 the bracket is so wide that 128
+ *     bins resolve the d/dx integrand only to ~1e-10 (more bins restore it),
+ *     and above x ~ 1e5 the FP32 bracket search rounds g(t_p) ~ -x.
  */
 #ifndef BESSEL_H
 #define BESSEL_H

@@ -183,9 +183,14 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
 
 // Domain conventions (see include/bessel.h).  Returns true when the element is
 // outside v real, 0 < x < inf; then logk, dv, dx hold the convention's values.
+// Smallest x the FP32 bracket search can represent: the upper end solves
+// x cosh t = L with L up to ~37 (FP64 margin), so L / x must stay below the
+// FP32 maximum.  Smaller positive x gives NaN (documented in the header).
+constexpr double kMinX = 1e-36;
+
 __device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
   const double nan_ = __builtin_nan("");
-  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0) {
+  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0 || (x > 0.0 && x < kMinX)) {
     logk = nan_; dv = nan_; dx = nan_;
     return true;
   }
@@ -234,25 +239,31 @@ constexpr int kPeakIters = 5;   // Newton steps for t_p
 constexpr int kUpperIters = 2;  // fixed-point steps before the final Newton step for t1
 constexpr int kLowerIters = 3;  // fixed-point steps for t0
 
+// The x cosh t and x sinh t terms below are formed as x e^{t} = 2^{t log2 e +
+// log2 x} and x e^{-t}, never as x times e^{t}: for x down to ~1e-30 the peak
+// and the upper end sit near t = log(2v/x) ~ 70-90, where e^{t} alone would
+// leave the FP32 range while x e^{t} stays moderate.  lx = log2 x.
+
 // Peak t_p > 0 when v^2 > x (Section 2.1).  g' = v tanh(v t) - x sinh t is
 // concave on t >= 0 (g''' <= 0), zero at 0 and at t_p, and g'(t) <= v - x sinh t
 // < 0 for t > asinh(v/x).  Newton steps started at asinh(v/x), right of the
 // root, on a concave function decreasing through the root stay right of it and
 // decrease monotonically; each step is clamped to [0, t] so FP32 rounding can
 // only stall it, never move it left of the root by more than the rounding.
-__device__ __forceinline__ float peak_f32(float v, float x) {
-  const float r = fminf(v * hrcp(x), 1e18f);
-  float t = kLn2F * hlog2(r + hsqrt(fmaf(r, r, 1.0f)));  // asinh(v/x)
+__device__ __forceinline__ float peak_f32(float v, float x, float lx) {
+  // asinh(r), r = v/x, without squaring r: log(r) + log(1 + sqrt(1 + 1/r^2))
+  const float rr = x * hrcp(v);
+  float t = kLn2F * (hlog2(v) - lx + hlog2(1.0f + hsqrt(fmaf(rr, rr, 1.0f))));
 #pragma unroll
   for (int k = 0; k < kPeakIters; ++k) {
     const float q = hexp2(-2.0f * kLog2eF * v * t);  // e^{-2 v t}
     const float rq = hrcp(1.0f + q);
     const float th = (1.0f - q) * rq;                  // tanh(v t)
     const float sech2 = 4.0f * q * rq * rq;            // sech^2(v t)
-    const float e = hexp2(kLog2eF * t);
-    const float ei = hrcp(e);
-    const float gp = v * th - 0.5f * x * (e - ei);     // g'(t)   (Eq. 4)
-    const float gpp = v * v * sech2 - 0.5f * x * (e + ei);  // g''(t)  (Eq. 5), < 0 here
+    const float xe = hexp2(fmaf(kLog2eF, t, lx));      // x e^{t}
+    const float xei = hexp2(fmaf(-kLog2eF, t, lx));    // x e^{-t}
+    const float gp = v * th - 0.5f * (xe - xei);       // g'(t)   (Eq. 4)
+    const float gpp = v * v * sech2 - 0.5f * (xe + xei);  // g''(t)  (Eq. 5), < 0 here
     const float tn = t - gp * hrcp(gpp);
     t = fminf(t, fmaxf(tn, 0.0f));
   }
@@ -265,20 +276,22 @@ __device__ __forceinline__ float peak_f32(float v, float x) {
 // because g'(t1) < 0); from t_p, inside the bracket, its iterates increase
 // toward t1.  A final Newton step from such an inside point of a concave F
 // lands at or beyond the root, so the returned t1 is outside.
-__device__ __forceinline__ float upper_f32(float v, float x, float tp, float G, float L) {
+__device__ __forceinline__ float upper_f32(float v, float x, float lx, float tp, float G, float L) {
   const float rx = hrcp(x);
   float t = tp;
 #pragma unroll
   for (int k = 0; k < kUpperIters; ++k) {
     const float y = fmaxf((log_cosh_f32(v * t) - G + L) * rx, 1.0f);
-    t = kLn2F * hlog2(y + hsqrt((y - 1.0f) * (y + 1.0f)));  // acosh(y)
+    // acosh(y) = log(y + sqrt(y - 1) sqrt(y + 1)): no y^2, which would
+    // overflow for y > 1.8e19 (x below ~1e-18)
+    t = kLn2F * hlog2(y + hsqrt(y - 1.0f) * hsqrt(y + 1.0f));
   }
   const float q = hexp2(-2.0f * kLog2eF * v * t);
   const float lc = v * t + (hlog2(1.0f + q) - 1.0f) * kLn2F;
-  const float e = hexp2(kLog2eF * t);
-  const float ei = hrcp(e);
-  const float F = lc - 0.5f * x * (e + ei) - G + L;
-  const float Fp = v * (1.0f - q) * hrcp(1.0f + q) - 0.5f * x * (e - ei);
+  const float xe = hexp2(fmaf(kLog2eF, t, lx));
+  const float xei = hexp2(fmaf(-kLog2eF, t, lx));
+  const float F = lc - 0.5f * (xe + xei) - G + L;
+  const float Fp = v * (1.0f - q) * hrcp(1.0f + q) - 0.5f * (xe - xei);
   const float tn = t - F * hrcp(Fp);
   // Fp < 0 strictly right of the peak; keep t if rounding made the step useless.
   return (Fp < 0.0f && tn >= t) ? tn : t;
@@ -288,14 +301,13 @@ __device__ __forceinline__ float upper_f32(float v, float x, float tp, float G, 
 // U(t) = acosh(exp(x cosh t + G - L)) / v is increasing with fixed point t0;
 // from t = 0 (outside, where F <= 0) its iterates increase toward t0 and stay
 // outside, so every iterate is a valid lower end.
-__device__ __forceinline__ float lower_f32(float v, float x, float tp, float G, float L) {
+__device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G, float L) {
   const float rv = hrcp(v);
   float t = 0.0f;
 #pragma unroll
   for (int k = 0; k < kLowerIters; ++k) {
-    const float e = hexp2(kLog2eF * t);
-    const float ch = 0.5f * (e + hrcp(e));
-    const float y = fmaxf(fmaf(x, ch, G - L), 0.0f);
+    const float xch = 0.5f * (hexp2(fmaf(kLog2eF, t, lx)) + hexp2(fmaf(-kLog2eF, t, lx)));  // x cosh t
+    const float y = fmaxf(xch + (G - L), 0.0f);
     // acosh(e^y) = y + log(1 + sqrt(1 - e^{-2y}))
     const float s = hsqrt(fmaxf(1.0f - hexp2(-2.0f * kLog2eF * y), 0.0f));
     t = (y + kLn2F * hlog2(1.0f + s)) * rv;
@@ -310,17 +322,18 @@ __device__ __forceinline__ float lower_f32(float v, float x, float tp, float G, 
 __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_eps_margin) {
   Bracket b;
   const float vf = (float)v, xf = (float)x;
+  const float lx = hlog2(xf);
   float tp = 0.0f;
-  if (v * v > x) tp = peak_f32(vf, xf);
+  if (v * v > x) tp = peak_f32(vf, xf, lx);
   const double G = g_f64(v, x, (double)tp);
   const float Gf = (float)G;
-  const float etp = hexp2(kLog2eF * tp);
-  const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + xf * (etp + hrcp(etp)));
+  const float xcp = hexp2(fmaf(kLog2eF, tp, lx)) + hexp2(fmaf(-kLog2eF, tp, lx));  // 2 x cosh t_p
+  const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + xcp);
   b.G = G;
   b.tp = tp;
-  b.t1 = upper_f32(vf, xf, tp, Gf, L);
+  b.t1 = upper_f32(vf, xf, lx, tp, Gf, L);
   const bool need_t0 = (-x - G + (double)L) <= 0.0;
-  b.t0 = need_t0 ? lower_f32(vf, xf, tp, Gf, L) : 0.0f;
+  b.t0 = need_t0 ? lower_f32(vf, lx, tp, Gf, L) : 0.0f;
   return b;
 }
 

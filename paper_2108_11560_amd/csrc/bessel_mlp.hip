@@ -206,11 +206,9 @@ __global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, i
 }
 
 // grad[e] = sum over blocks of partial[b][e] in block order; loss likewise.
-__global__ __launch_bounds__(kBlock) void k_mlp_reduce(const float* __restrict__ partial, int nblocks,
-                                                       float* __restrict__ grad, float* __restrict__ loss) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e > kNW) return;
-  // blocks in order (deterministic); eight loads in flight per group
+// Sum over blocks of value e of the partials, in block order (deterministic);
+// eight loads in flight per group.
+__device__ __forceinline__ float reduce_partials(const float* __restrict__ partial, int nblocks, int e) {
   double acc = 0.0;
   int b = 0;
   for (; b + 8 <= nblocks; b += 8) {
@@ -221,17 +219,22 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce(const float* __restrict__
     for (int j = 0; j < 8; ++j) acc += (double)p[j];
   }
   for (; b < nblocks; ++b) acc += (double)partial[(int64_t)b * (kNW + 1) + e];
-  if (e < kNW) grad[e] = (float)acc;
-  else if (loss) *loss = (float)acc;
+  return (float)acc;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_reduce(const float* __restrict__ partial, int nblocks,
+                                                       float* __restrict__ grad, float* __restrict__ loss) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e > kNW) return;
+  const float g = reduce_partials(partial, nblocks, e);
+  if (e < kNW) grad[e] = g;
+  else if (loss) *loss = g;
 }
 
 // Adam (Kingma & Ba) with bias correction; step counts from 1.
-__global__ __launch_bounds__(kBlock) void k_mlp_adam(float* __restrict__ P, const float* __restrict__ grad,
-                                                     float* __restrict__ m, float* __restrict__ s2, int64_t step,
-                                                     float lr, float beta1, float beta2, float eps) {
-  const int e = blockIdx.x * kBlock + threadIdx.x;
-  if (e >= kNW) return;
-  const float g = grad[e];
+__device__ __forceinline__ void adam_update(float* __restrict__ P, float g, float* __restrict__ m,
+                                            float* __restrict__ s2, int e, int64_t step, float lr, float beta1,
+                                            float beta2, float eps) {
   const float mm = beta1 * m[e] + (1.0f - beta1) * g;
   const float ss = beta2 * s2[e] + (1.0f - beta2) * g * g;
   m[e] = mm;
@@ -239,6 +242,30 @@ __global__ __launch_bounds__(kBlock) void k_mlp_adam(float* __restrict__ P, cons
   const float mh = mm / (1.0f - powf(beta1, (float)step));
   const float sh = ss / (1.0f - powf(beta2, (float)step));
   P[e] -= lr * mh / (sqrtf(sh) + eps);
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_adam(float* __restrict__ P, const float* __restrict__ grad,
+                                                     float* __restrict__ m, float* __restrict__ s2, int64_t step,
+                                                     float lr, float beta1, float beta2, float eps) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e >= kNW) return;
+  adam_update(P, grad[e], m, s2, e, step, lr, beta1, beta2, eps);
+}
+
+// One training step's tail in one launch: the ordered reduction of the block
+// partials and the Adam update of each parameter; the batch loss goes to *loss.
+__global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float* __restrict__ partial, int nblocks,
+                                                            float* __restrict__ P, float* __restrict__ m,
+                                                            float* __restrict__ s2, int64_t step, float lr,
+                                                            float beta1, float beta2, float eps,
+                                                            float* __restrict__ loss) {
+  const int e = blockIdx.x * kBlock + threadIdx.x;
+  if (e > kNW) return;
+  const float g = reduce_partials(partial, nblocks, e);
+  if (e < kNW)
+    adam_update(P, g, m, s2, e, step, lr, beta1, beta2, eps);
+  else
+    *loss = g;
 }
 
 // ---------------------------------------------------------------------------
@@ -696,17 +723,27 @@ extern "C" int bessel_mlp_get_params(const bessel_mlp* m, float* params, int64_t
   return BESSEL_OK;
 }
 
-static int launch_grad(bessel_mlp* m, int64_t n, int64_t batch, int sampled, uint64_t seed, int64_t step,
-                       const float* v, const float* x, const float* t0, const float* t1, float alpha,
-                       hipStream_t st) {
-  const int64_t nblocks = (batch + kTB - 1) / kTB;
+// Per-block partial gradients of a batch (k_mlp_grad); returns the block count.
+static int launch_partials(bessel_mlp* m, int64_t n, int64_t batch, int sampled, uint64_t seed, int64_t step,
+                           const float* v, const float* x, const float* t0, const float* t1, float alpha,
+                           hipStream_t st, int64_t& nblocks) {
+  nblocks = (batch + kTB - 1) / kTB;
   int rc = ensure(m->partial, m->cap_partial_blocks, nblocks * (kNW + 1), st, "partial gradients");
   if (rc) return rc;
   k_mlp_grad<<<dim3((unsigned)nblocks), kTB, 0, st>>>(m->params, n, batch, sampled, seed, step, v, x, t0, t1,
                                                       alpha, m->partial);
+  return check_launch("k_mlp_grad");
+}
+
+static int launch_grad(bessel_mlp* m, int64_t n, int64_t batch, int sampled, uint64_t seed, int64_t step,
+                       const float* v, const float* x, const float* t0, const float* t1, float alpha,
+                       hipStream_t st) {
+  int64_t nblocks = 0;
+  int rc = launch_partials(m, n, batch, sampled, seed, step, v, x, t0, t1, alpha, st, nblocks);
+  if (rc) return rc;
   k_mlp_reduce<<<dim3((kNW + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->partial, (int)nblocks, m->grad,
                                                                         m->grad + kNW);
-  return check_launch("k_mlp_grad");
+  return check_launch("k_mlp_reduce");
 }
 
 extern "C" int bessel_mlp_loss_grad(bessel_mlp* m, int64_t n, const float* v, const float* x, const float* t0,
@@ -741,20 +778,21 @@ extern "C" int bessel_mlp_train(bessel_mlp* m, const bessel_mlp_train_cfg* cfg, 
   k_mlp_labels<<<grid, kBlock, 0, st>>>(n, v, x, t0, t1);
   rc = check_launch("k_mlp_labels");
   if (rc) return rc;
+  // two launches per step: partial gradients, then the ordered reduction
+  // fused with the Adam update (which also records the step's loss)
   for (int64_t k = 0; k < cfg->steps; ++k) {
-    rc = launch_grad(m, n, cfg->batch, 1, cfg->seed, k, v, x, t0, t1, cfg->alpha, st);
+    int64_t nblocks = 0;
+    rc = launch_partials(m, n, cfg->batch, 1, cfg->seed, k, v, x, t0, t1, cfg->alpha, st, nblocks);
     if (rc) return rc;
-    hipError_t e = hipMemcpyAsync(m->losses + k, m->grad + kNW, sizeof(float), hipMemcpyDeviceToDevice, st);
-    if (e != hipSuccess) return hip_fail(e, "loss copy");
     // exponential decay from lr to lr_final over the run
     const double frac = cfg->steps > 1 ? (double)k / (double)(cfg->steps - 1) : 0.0;
     const float lr = (float)(cfg->lr * pow((double)cfg->lr_final / (double)cfg->lr, frac));
     m->adam_step += 1;
-    k_mlp_adam<<<dim3((kNW + kBlock - 1) / kBlock), kBlock, 0, st>>>(m->params, m->grad, m->adam_m, m->adam_s,
-                                                                     m->adam_step, lr, cfg->beta1, cfg->beta2,
-                                                                     cfg->adam_eps);
+    k_mlp_reduce_adam<<<dim3((kNW + 1 + kBlock - 1) / kBlock), kBlock, 0, st>>>(
+        m->partial, (int)nblocks, m->params, m->adam_m, m->adam_s, m->adam_step, lr, cfg->beta1, cfg->beta2,
+        cfg->adam_eps, m->losses + k);
     m->packed_stale = true;
-    rc = check_launch("k_mlp_adam");
+    rc = check_launch("k_mlp_reduce_adam");
     if (rc) return rc;
   }
   if (loss_host && cfg->steps > 0) {

@@ -1,0 +1,37 @@
+"""Write domain_points.json: the oracle's log K_v(x), d/dv and d/dx at the
+corners of the domain the GPU path is validated on (and a little beyond).
+
+    python tests/golden/make_domain_points.py
+
+Calls only the oracle (oracle/, long-double adaptive quadrature of Eq. (1)-(2)
+and Eq. (13)).  x = 1e10 is left out: the oracle's adaptive rule cannot meet
+its tolerance there in reasonable time."""
+
+import json
+import os
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, os.path.dirname(os.path.dirname(HERE)))
+
+import numpy as np  # noqa: E402
+
+import oracle  # noqa: E402
+
+V = [0.0, 1e-10, 0.5, 10.0, 100.0, 1000.0]
+X = [1e-35, 1e-30, 1e-20, 1e-12, 1e-6, 1e-3, 1.0, 1e3, 1e4, 1e5, 3e5, 1e6]
+
+
+def main():
+    vv, xx = (a.ravel() for a in np.meshgrid(V, X, indexing="ij"))
+    lk, dv, dx = oracle.logk(vv, xx, deriv=True)
+    points = [{"v": float(a), "x": float(b), "logk": float(c), "dv": float(d), "dx": float(e)}
+              for a, b, c, d, e in zip(vv, xx, lk, dv, dx)]
+    out = {"source": "oracle/oracle.c oracle_logk_batch (this script)", "points": points}
+    with open(os.path.join(HERE, "domain_points.json"), "w") as f:
+        json.dump(out, f, indent=1)
+    print(len(points), "points")
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,77 @@
+"""The GPU path at the corners of its validated domain and beyond, against
+stored oracle values (tests/golden/domain_points.json, written by
+make_domain_points.py, which calls only the oracle).
+
+Validated (the bars of the path, mixed error, 128 bins): |v| <= 1e3 and
+1e-6 <= x <= 1e5 in FP64 (1e-12), 1e-35 <= x <= 1e5 in FP32 (1e-5).  Beyond
+(1e-35 <= x < 1e-6 in FP64, and x up to 1e6) the results are finite and within
+the looser bounds measured for them (FP64: 1e-8 on log K, 1e-4 on the
+derivatives); x below 1e-36 gives NaN by convention.
+"""
+
+import json
+import os
+
+import numpy as np
+import pytest
+import torch
+
+pytestmark = pytest.mark.gpu
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+PTS = json.load(open(os.path.join(HERE, "golden", "domain_points.json")))["points"]
+
+
+@pytest.fixture(scope="module")
+def bk():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    import paper_2108_11560_amd as mod
+    mod.load()
+    return mod
+
+
+def run(bk, dt, split):
+    v = np.array([p["v"] for p in PTS])
+    x = np.array([p["x"] for p in PTS])
+    ref = np.array([[p["logk"], p["dv"], p["dx"]] for p in PTS])
+    prev = bk.set_split_threshold(1 << 20 if split else 0)
+    try:
+        vt = torch.tensor(v, dtype=dt, device="cuda")
+        xt = torch.tensor(x, dtype=dt, device="cuda")
+        got = np.stack([t.double().cpu().numpy() for t in bk.logk_dv_dx(vt, xt)], axis=1)
+    finally:
+        bk.set_split_threshold(prev)
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    return v, x, got, err
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_fp64_domain(bk, split):
+    v, x, got, err = run(bk, torch.float64, split)
+    assert np.isfinite(got).all()
+    inside = (x >= 1e-6) & (x <= 1e5)
+    for i in np.flatnonzero(inside):
+        assert err[i].max() <= 1e-12, (v[i], x[i], err[i])
+    for i in np.flatnonzero(~inside):
+        assert err[i, 0] <= 1e-8 and err[i, 1:].max() <= 1e-4, (v[i], x[i], err[i])
+
+
+@pytest.mark.parametrize("split", [False, True])
+def test_fp32_domain(bk, split):
+    v, x, got, err = run(bk, torch.float32, split)
+    assert np.isfinite(got).all()
+    inside = x <= 1e5
+    for i in np.flatnonzero(inside):
+        assert err[i].max() <= 1e-5, (v[i], x[i], err[i])
+    for i in np.flatnonzero(~inside):
+        assert err[i, 0] <= 1e-5 and err[i, 1:].max() <= 1e-4, (v[i], x[i], err[i])
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_below_range_is_nan(bk, dt):
+    x = torch.tensor([1e-37, 5e-37, 2e-36], dtype=torch.float64).to(dt).cuda()
+    v = torch.ones_like(x)
+    lk, dv, dx = bk.logk_dv_dx(v, x)
+    assert torch.isnan(lk[:2]).all() and torch.isnan(dv[:2]).all() and torch.isnan(dx[:2]).all()
+    assert torch.isfinite(lk[2])
