@@ -3,7 +3,8 @@
 Run as ``python -m paper_2108_11560_amd.build``; ``__graft_entry__.build()``
 calls :func:`build` too.  Every HIP source is compiled for gfx950 only, with
 packed FP32 instructions disabled (``-packed-fp32-ops``).  Also builds the
-instruction-rate microbenchmark ``_build/valu_rates`` (``microbench/``).
+instruction-rate microbenchmark ``_build/valu_rates`` (``microbench/``) and
+the plain-C example ``_build/c_abi_demo`` (``examples/``).
 """
 
 from __future__ import annotations
@@ -22,6 +23,9 @@ LIB = os.path.join(HERE, "libbessel.so")
 SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip", "bessel_gh.hip"]
 # stand-alone programs: name -> source (relative to the package)
 PROGRAMS = {"valu_rates": os.path.join("microbench", "valu_rates.hip")}
+# C programs against the C ABI (plain C, linked to libbessel.so)
+C_PROGRAMS = {"c_abi_demo": os.path.join("examples", "c_abi_demo.c")}
+ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
 
 ARCH = "gfx950"
 
@@ -67,6 +71,15 @@ def build(verbose: bool = False) -> str:
     os.replace(tmp, LIB)
     for name, src in PROGRAMS.items():
         cmd = [hipcc(), *HIP_FLAGS, os.path.join(HERE, src), "-o", os.path.join(objdir, name)]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        subprocess.run(cmd, check=True)
+    for name, src in C_PROGRAMS.items():
+        # the HIP runtime header needs its platform macro when read by a C compiler
+        cmd = ["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__", "-I", INCLUDE,
+               "-I", os.path.join(ROCM, "include"), os.path.join(HERE, src), "-o", os.path.join(objdir, name),
+               "-L", HERE, "-lbessel", "-L", os.path.join(ROCM, "lib"), "-lamdhip64", "-lm",
+               "-Wl,-rpath,$ORIGIN/.."]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.run(cmd, check=True)
