@@ -19,6 +19,8 @@ Entry points (all vectorised over float64 arrays of equal length):
   paper's order (readings documented in ``oracle.c``).
 * :func:`trapezoid_brute` -- a single-element plain trapezoid with a huge bin
   count, used only to pin the adaptive rule.
+* :func:`logdk` -- log |d^a/dv^a d^b/dx^b K_v(x)| and its sign for any orders
+  (Section 4.1, Eq. (13)), each integrand over its own peak and interval.
 """
 
 from __future__ import annotations
@@ -69,6 +71,8 @@ def _load():
             ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_double, ctypes.c_int64, dp,
         ]
         lib.oracle_trapezoid_brute.restype = ctypes.c_int
+        lib.oracle_logdk_batch.argtypes = [ctypes.c_int64, dp, dp, ctypes.c_int, ctypes.c_int, dp, dp, ctypes.c_int]
+        lib.oracle_logdk_batch.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -160,3 +164,19 @@ def trapezoid_brute(v: float, x: float, lo: float, hi: float, nbins: int):
     if rc != 0:
         raise ValueError("oracle_trapezoid_brute rejected its arguments")
     return out
+
+
+def logdk(v, x, order_v: int, order_x: int, nthreads: int | None = None):
+    """(log |D|, sign D) for D = d^order_v/dv^order_v d^order_x/dx^order_x K_v(x)
+    (Section 4.1, Eq. (13)); sign is (-1)^order_x, times sign(v) for odd
+    order_v, and 0 where D is exactly zero (odd order_v at v = 0)."""
+    lib = _load()
+    v, x = np.broadcast_arrays(_arr(v), _arr(x))
+    v, x = _arr(v), _arr(x)
+    n = v.size
+    out, sign = np.empty(n), np.empty(n)
+    rc = lib.oracle_logdk_batch(n, _ptr(v), _ptr(x), int(order_v), int(order_x), _ptr(out), _ptr(sign),
+                                nthreads or default_threads())
+    if rc != 0:
+        raise ValueError("oracle_logdk_batch rejected its arguments")
+    return out, sign
