@@ -15,6 +15,7 @@ resident in HBM before timing.  Each path is timed over the whole batch at
     f32_fwd_bwd
     f32_hess
     gh_f32_fwd_bwd   per-set sums over 1024 sets x 65536 samples with gradients
+    f64_logdk_1_1    d2K/dvdx with its own peak and bracket (bessel_logdk), FP64
 
 The predictor is trained (20000 Adam steps on 2^20 Newton brackets) and its
 margins calibrated before any timing.  Every launch runs on torch's current
@@ -247,6 +248,11 @@ def main():
         ms_h = time_path(hs, max(1, args.steps // 2), args.warmup)
         paths[f"{dt}_hess"] = {"ms": ms_h, "evals_per_s": args.n / (ms_h * 1e-3)}
 
+    # general derivative, each integrand over its own bracket: orders (1, 1)
+    dk = lambda: bk.logdk(V["f64"], X["f64"], 1, 1, nbins=nb, want_sign=False)  # noqa: E731
+    ms_d = time_path(dk, max(1, args.steps // 4), max(1, args.warmup))
+    paths["f64_logdk_1_1"] = {"ms": ms_d, "evals_per_s": args.n / (ms_d * 1e-3)}
+
     fwd = lambda: bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
     fb = lambda: bk.logk_dv_dx(V["f32"], X["f32"], grad_out=GO["f32"], nbins=nb, range="mlp", mlp=mlp)  # noqa: E731
     ms_f = time_path(fwd, args.steps, args.warmup)
@@ -270,7 +276,7 @@ def main():
                                "valu_frac": alg_slots("f32", True, nb) * n_gh / (ms_g * 1e-3) / PEAK_SLOTS}
 
     for key, p in paths.items():
-        if key.startswith("gh"):
+        if key.startswith(("gh", "f64_logdk")):
             continue
         der = 2 if key.endswith("hess") else 1 if key.endswith("bwd") else 0
         if "mlp" in key:

@@ -64,6 +64,7 @@ extern "C" {
 #define BESSEL_ERR_HIP (-5)        /* a HIP launch or runtime call failed */
 #define BESSEL_ERR_ALIAS (-6)      /* an output overlaps an input */
 #define BESSEL_ERR_UNSUPPORTED (-7) /* combination not provided (e.g. MLP range with F64) */
+#define BESSEL_ERR_ORDER (-8)      /* derivative order outside [0, BESSEL_MAX_ORDER] */
 
 #define BESSEL_MIN_BINS 2
 #define BESSEL_MAX_BINS 4096
@@ -125,6 +126,31 @@ int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, v
  */
 int bessel_logk_hess(int dtype, int64_t n, const void* v, const void* x, void* logk, void* dv, void* dx, void* dvv,
                      void* dxx, void* dvx, int nbins, void* hip_stream);
+
+/*
+ * bessel_logdk -- derivatives of K itself of any orders, each integrand over
+ * its own peak and bracket (Section 4.1, Eq. (13)):
+ *   logdk[i] = log |d^a/dv^a d^b/dx^b K_v(x)|  at (v[i], x[i]),
+ *   a = order_v, b = order_x, both in [0, BESSEL_MAX_ORDER];
+ *   sign[i]  (nullable) = the derivative's sign: (-1)^b, times sign(v) for odd
+ *            a, and 0 where it is exactly zero (odd a at v = 0).
+ * The derivative is (-1)^b times the integral of
+ *   t^a cosh^b(t) C(v t) e^{-x cosh t}  over t >= 0, C = cosh (even a) or sinh (odd a),
+ * and each element locates that integrand's own peak and the interval where it
+ * is within eps of it (a doubling search from the peak for each end, then
+ * bisection and Newton steps), and sums nbins trapezoid bins relative to the
+ * peak.  Unlike the companion sums of bessel_logk_dv_dx / bessel_logk_hess,
+ * which use f's interval, this keeps its accuracy for high orders.  FP64
+ * arithmetic for both dtypes (the dtype sets the arrays and eps).
+ * Conventions: NaN v or x, x < 0 or 0 < x < 1e-36 -> NaN (sign NaN); odd a at
+ * v == 0 -> -inf (sign 0); x == 0 or |v| == inf -> +inf; x == +inf -> -inf.
+ * Validated domain: as log K (F64: |v| <= 1e3, 1e-6 <= x <= 1e5, mixed error
+ * 1e-12 on logdk at 128 bins; orders up to BESSEL_MAX_ORDER).  Outputs may not
+ * overlap inputs or each other.
+ */
+#define BESSEL_MAX_ORDER 8
+int bessel_logdk(int dtype, int64_t n, const void* v, const void* x, int order_v, int order_x, void* logdk,
+                 void* sign, int nbins, void* hip_stream);
 
 /*
  * bessel_set_split_threshold -- batch-size policy of bessel_logk and

@@ -15,6 +15,8 @@ computation runs in the library's kernels.
     logk(v, x, nbins=128)                  -> log K_v(x)
     logk_dv_dx(v, x, grad_out=None, ...)   -> (log K, d/dv log K, d/dx log K)
     logk_hess(v, x)                        -> (log K, d/dv, d/dx, d2/dv2, d2/dx2, d2/dvdx)
+    logdk(v, x, a, b)                      -> (log |d^a/dv^a d^b/dx^b K|, its sign), each
+                                              integrand over its own peak and bracket
     bessel_range(v, x)                     -> (t0, t1, t_p, g(t_p))
     log_bessel_k(v, x)                     -> log K with autograd (BesselLogK),
                                               twice differentiable on the Newton bracket
@@ -34,6 +36,7 @@ __all__ = [
     "logk",
     "logk_dv_dx",
     "logk_hess",
+    "logdk",
     "set_split_threshold",
     "bessel_range",
     "log_bessel_k",
@@ -138,6 +141,21 @@ def logk_hess(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, want=(True,) *
                                   _stream_ptr(v.device))
     check(rc, "bessel_logk_hess")
     return tuple(outs)
+
+
+def logdk(v: torch.Tensor, x: torch.Tensor, order_v: int, order_x: int, nbins: int = 128, want_sign: bool = True):
+    """(log |D|, sign of D) for D = d^order_v/dv^order_v d^order_x/dx^order_x K_v(x),
+    each derivative integrand over its own peak and bracket (Section 4.1,
+    Eq. (13)); the sign comes back None when ``want_sign`` is False."""
+    v, x = _check_pair(v, x)
+    out = torch.empty_like(v)
+    sgn = torch.empty_like(v) if want_sign else None
+    lib = load()
+    with _on(v.device):
+        rc = lib.bessel_logdk(_dtype_code(v), v.numel(), _ptr(v), _ptr(x), int(order_v), int(order_x), _ptr(out),
+                              _ptr(sgn), int(nbins), _stream_ptr(v.device))
+    check(rc, "bessel_logdk")
+    return out, sgn
 
 
 def set_split_threshold(n: int) -> int:

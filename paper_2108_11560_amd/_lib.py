@@ -26,6 +26,7 @@ STATUS = {
     -5: "BESSEL_ERR_HIP",
     -6: "BESSEL_ERR_ALIAS",
     -7: "BESSEL_ERR_UNSUPPORTED",
+    -8: "BESSEL_ERR_ORDER",
 }
 
 # Every symbol include/bessel.h declares, with its ctypes signature.
@@ -39,6 +40,7 @@ SIGNATURES = {
     "bessel_logk_backward": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp]),
     "bessel_logk_hess": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _vp]),
     "bessel_hess_vjp": (_int, [_int, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]),
+    "bessel_logdk": (_int, [_int, _i64, _vp, _vp, _int, _int, _vp, _vp, _int, _vp]),
     "bessel_set_split_threshold": (_int, [_i64, _vp]),
     "bessel_mlp_create": (_int, [_vp, _i64, _vp]),
     "bessel_mlp_destroy": (_int, [_vp]),

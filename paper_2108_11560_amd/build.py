@@ -20,7 +20,7 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libbessel.so")
 
-SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip", "bessel_gh.hip"]
+SOURCES = ["bessel_kernels.hip", "bessel_mlp.hip", "bessel_gh.hip", "bessel_deriv.hip"]
 # stand-alone programs: name -> source (relative to the package)
 PROGRAMS = {"valu_rates": os.path.join("microbench", "valu_rates.hip")}
 # C programs against the C ABI (plain C, linked to libbessel.so)

@@ -153,3 +153,20 @@ def test_split_threshold_setter(lib):
     old = prev.value
     assert lib.bessel_set_split_threshold(old, ctypes.byref(prev)) == 0
     assert prev.value == 77
+
+
+def test_logdk_argument_errors(lib):
+    # dtype, n, v, x, order_v, order_x, logdk, sign, nbins, stream
+    assert lib.bessel_logdk(5, 4, FAKE_A, FAKE_B, 1, 0, FAKE_C, NULL, 128, NULL) == -2
+    assert lib.bessel_logdk(1, -1, FAKE_A, FAKE_B, 1, 0, FAKE_C, NULL, 128, NULL) == -1
+    assert lib.bessel_logdk(1, 4, NULL, FAKE_B, 1, 0, FAKE_C, NULL, 128, NULL) == -1
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 9, 0, FAKE_C, NULL, 128, NULL) == -8
+    assert "orders" in err(lib)
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 0, -1, FAKE_C, NULL, 128, NULL) == -8
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 1, 0, FAKE_C, NULL, 1, NULL) == -3
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 1, 0, NULL, NULL, 128, NULL) == -1
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 1, 0, FAKE_A, NULL, 128, NULL) == -6
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 1, 0, FAKE_C, FAKE_B, 128, NULL) == -6
+    assert lib.bessel_logdk(1, 4, FAKE_A, FAKE_B, 1, 0, FAKE_C, FAKE_C, 128, NULL) == -6
+    assert lib.bessel_logdk(1, 0, NULL, NULL, 8, 8, NULL, NULL, 128, NULL) == 0
+    assert _lib.STATUS[-8] == "BESSEL_ERR_ORDER"

@@ -110,6 +110,18 @@ def accuracy_grid():
     return V.ravel(), X.ravel()
 
 
+def domain_pairs(n: int, seed: int = 31):
+    """Pairs across the validated FP64 domain: half with v ~ U[0, 1e3], half
+    with v ~ LogU[1e-8, 1] (orders near 0), x ~ LogU[1e-6, 1e5] throughout;
+    the two halves interleaved."""
+    rng = np.random.default_rng(seed)
+    big = rng.uniform(0.0, 1e3, n)
+    small = 10.0 ** rng.uniform(-8.0, 0.0, n)
+    v = np.where(np.arange(n) % 2 == 0, big, small)
+    x = 10.0 ** rng.uniform(-6.0, 5.0, n)
+    return v, x
+
+
 def to_f32(a: np.ndarray) -> np.ndarray:
     """Round float64 draws to the nearest float32."""
     return np.asarray(a, dtype=np.float64).astype(np.float32)
