@@ -63,21 +63,21 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 # HBM bytes per element of the learned-range call (fused kernel + fallback)
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
-# its size on this counter) plus WRITE_SIZE, taken on the kernel sources whose
-# hash is recorded here; reported only while the sources still match.
-TRAFFIC = {"sources_sha256": "44b210e58f988145a8869b06a48a4eb32a8cc6ca6d205bd36933bfb46eb486a6",
+# its size on this counter) plus WRITE_SIZE, taken on the sources the two
+# kernels are compiled from (hashed below); reported only while they still match.
+TRAFFIC = {"sources_sha256": "cfef8989566ddbdf9a712bce5aa83e435300036814c374541f0ccfc1ad352016",
            # fused (65679 * 2 + 65800 KiB) + fallback (735 * 2 + 169 KiB) per 2^24 elements
            "bytes_per_elem": 12.134}
+TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp")
 
 
 def kernel_sources_sha256() -> str:
     import hashlib
     csrc = os.path.join(ROOT, "paper_2108_11560_amd", "csrc")
     h = hashlib.sha256()
-    for name in sorted(os.listdir(csrc)):
-        if name.endswith((".hip", ".hpp")):
-            with open(os.path.join(csrc, name), "rb") as f:
-                h.update(name.encode() + b"\0" + f.read())
+    for name in TRAFFIC_SOURCES:
+        with open(os.path.join(csrc, name), "rb") as f:
+            h.update(name.encode() + b"\0" + f.read())
     return h.hexdigest()
 
 
