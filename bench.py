@@ -51,10 +51,11 @@ W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
           ("f64", 0): 24.5, ("f64", 1): 30.5, ("f64", 2): 36.5}
 W_PRE = 500.0
 # Learned bracket: the network's VALU work (128 activations 1 / (1 + 2^a) at
-# 5 slots, 128 layer-3 FMAs, features 6, bf16 packing 32, outputs 4; its 48
-# MFMAs per 64 elements run on the matrix cores and are not counted) plus
-# bracket 10, shift 35, bin set-up 120, check 10, final 50, loads 30.
-W_NET = 810.0
+# 5 slots, bf16 packing of the 128 activations two per instruction 64,
+# features 6, outputs 4; its three layers' 56 MFMAs per 64 elements run on the
+# matrix cores and are not counted) plus bracket 10, shift 35, bin set-up 120,
+# check 10, final 50, loads 30.
+W_NET = 714.0
 W_MLP_PRE = W_NET + 255.0
 
 # MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s

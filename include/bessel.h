@@ -9,8 +9,10 @@
  * Each element: find the peak t_p of g(t) = log cosh(v t) - x cosh t
  * (Section 2.2), bracket [t0, t1] = {t : g(t) >= g(t_p) + log eps} (Section 2.1,
  * Eq. (7)-(8); Section 2.3), and sum a fixed number of trapezoid bins in log
- * space (Section 2.4, Eq. (9)-(11) and Eq. (int)).  Derivatives come from the
- * companion integrals of Section 4.1, Eq. (13), over the same bins.
+ * space (Section 2.4, Eq. (9)-(11) and Eq. (int)).  Derivatives of log K up
+ * to second order come from the companion integrals of Section 4.1, Eq. (13),
+ * over the same bins; bessel_logdk gives derivatives of K of higher orders,
+ * each integrand over its own peak and bracket.
  *
  * Conventions shared by every entry point:
  *   - Array pointers are DEVICE pointers, contiguous, owned by the caller; the
@@ -199,8 +201,8 @@ int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void*
  * ((log max(|v|, 1e-3) - m_v)/s_v, (log x - m_x)/s_x), to (y0, y1); the bracket
  * is t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1).  It is trained
  * on the method's own Newton brackets (Sections 2.2-2.3 at the FP32 eps), and
- * at inference (layers 1 and 2 on bf16 MFMA, layer 3 in FP32) every predicted
- * bracket is checked after the bins: the end terms must lie below eps
+ * at inference (all three layers on bf16 MFMA with FP32 accumulation) every
+ * predicted bracket is checked after the bins: the end terms must lie below eps
  * relative to the shift and the even-node and odd-node sums must agree to
  * 1e-5.  Elements that fail are recomputed by the Newton path in a second
  * kernel on the same stream.
