@@ -16,6 +16,8 @@ resident in HBM before timing.  Each path is timed over the whole batch at
     f32_hess
     gh_f32_fwd_bwd   per-set sums over 1024 sets x 65536 samples with gradients
     f64_logdk_1_1    d2K/dvdx with its own peak and bracket (bessel_logdk), FP64
+    f32_mlp_table_fwd, f32_mlp_table_fwd_bwd
+                     the learned bracket read from the network's bilinear table
 
 The predictor is trained (20000 Adam steps on 2^20 Newton brackets) and its
 margins calibrated before any timing.  Every launch runs on torch's current
@@ -57,6 +59,10 @@ W_PRE = 500.0
 # check 10, final 50, loads 30.
 W_NET = 714.0
 W_MLP_PRE = W_NET + 255.0
+# The same network read from its bilinear table: features 8, cell index 12,
+# two 16-byte loads, 6 FMAs, in place of the network's VALU work.
+W_TAB = 30.0
+W_TAB_PRE = W_TAB + 255.0
 
 # MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s
 # (= the 78.6 TFLOP/s FP64 / unpacked-FP32 vector peak with an FMA as 2 FLOP).
@@ -86,10 +92,11 @@ def alg_slots(dt: str, der: int, nbins: int) -> float:
     return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE
 
 
-def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float) -> float:
-    """Per element of a learned-range call: the fused kernel's work, plus the
-    Newton path for the fallback fraction."""
-    return (nbins + 1) * W_NODE[("f32", int(grad))] + W_MLP_PRE + fallback_rate * alg_slots("f32", grad, nbins)
+def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float, pre: float = W_MLP_PRE) -> float:
+    """Per element of a learned-range call: the fused kernel's work (pre: its
+    per-element work outside the bins), plus the Newton path for the fallback
+    fraction."""
+    return (nbins + 1) * W_NODE[("f32", int(grad))] + pre + fallback_rate * alg_slots("f32", grad, nbins)
 
 
 def parse():
@@ -262,6 +269,16 @@ def main():
     fb_bwd = mlp.fallback_count()
     paths["f32_mlp_fwd"] = {"ms": ms_f, "evals_per_s": args.n / (ms_f * 1e-3), "fallback_rate": fb_fwd / args.n}
     paths["f32_mlp_fwd_bwd"] = {"ms": ms_b, "evals_per_s": args.n / (ms_b * 1e-3), "fallback_rate": fb_bwd / args.n}
+    fwd = lambda: bk.logk(V["f32"], X["f32"], nbins=nb, range="mlp_table", mlp=mlp)  # noqa: E731
+    fb = lambda: bk.logk_dv_dx(V["f32"], X["f32"], grad_out=GO["f32"], nbins=nb, range="mlp_table",  # noqa: E731
+                               mlp=mlp)
+    ms_tf = time_path(fwd, args.steps, args.warmup)
+    fb_tf = mlp.fallback_count()
+    ms_tb = time_path(fb, args.steps, args.warmup)
+    fb_tb = mlp.fallback_count()
+    paths["f32_mlp_table_fwd"] = {"ms": ms_tf, "evals_per_s": args.n / (ms_tf * 1e-3), "fallback_rate": fb_tf / args.n}
+    paths["f32_mlp_table_fwd_bwd"] = {"ms": ms_tb, "evals_per_s": args.n / (ms_tb * 1e-3),
+                                      "fallback_rate": fb_tb / args.n}
     mlp_info = {"train_steps": args.mlp_steps, "train_seconds": t_train,
                 "final_loss": float(losses[-1]) if losses.size else None, "loaded_from": args.load_mlp,
                 "margin_t1": m1, "margin_t0": m0, "calibration_fallback_rate": cal_rate}
@@ -280,7 +297,9 @@ def main():
         if key.startswith(("gh", "f64_logdk")):
             continue
         der = 2 if key.endswith("hess") else 1 if key.endswith("bwd") else 0
-        if "mlp" in key:
+        if "mlp_table" in key:
+            p["alg_slots_per_elem"] = alg_slots_mlp(der == 1, nb, p["fallback_rate"], pre=W_TAB_PRE)
+        elif "mlp" in key:
             p["alg_slots_per_elem"] = alg_slots_mlp(der == 1, nb, p["fallback_rate"])
         else:
             p["alg_slots_per_elem"] = alg_slots(key[:3], der, nb)

@@ -56,13 +56,14 @@ extern "C" {
 /* how [t0, t1] is found */
 #define BESSEL_RANGE_NEWTON 0 /* peak by Newton steps, ends by monotone fixed-point + Newton steps */
 #define BESSEL_RANGE_MLP 1    /* learned bracket with a per-element check and Newton fallback */
+#define BESSEL_RANGE_MLP_TABLE 2 /* the same network read from its bilinear table (see bessel_mlp) */
 
 /* status codes */
 #define BESSEL_OK 0
 #define BESSEL_ERR_ARG (-1)        /* NULL required pointer, n < 0 */
 #define BESSEL_ERR_DTYPE (-2)      /* dtype not BESSEL_F32 / BESSEL_F64 */
 #define BESSEL_ERR_NBINS (-3)      /* nbins outside [BESSEL_MIN_BINS, BESSEL_MAX_BINS] */
-#define BESSEL_ERR_RANGE_MODE (-4) /* unknown range_mode, or BESSEL_RANGE_MLP with mlp == NULL */
+#define BESSEL_ERR_RANGE_MODE (-4) /* unknown range_mode, or a learned range_mode with mlp == NULL */
 #define BESSEL_ERR_HIP (-5)        /* a HIP launch or runtime call failed */
 #define BESSEL_ERR_ALIAS (-6)      /* an output overlaps an input */
 #define BESSEL_ERR_UNSUPPORTED (-7) /* combination not provided (e.g. MLP range with F64) */
@@ -80,8 +81,8 @@ typedef struct bessel_mlp bessel_mlp;
  *   logk     [n] output (dtype).
  *   nbins    number of trapezoid bins n of Eq. (9) (n + 1 nodes); 64, 128 and
  *            256 run specialised kernels, other values in range a generic one.
- *   range_mode, mlp   BESSEL_RANGE_NEWTON (mlp ignored, may be NULL) or
- *            BESSEL_RANGE_MLP (mlp required; F32 only).
+ *   range_mode, mlp   BESSEL_RANGE_NEWTON (mlp ignored, may be NULL),
+ *            BESSEL_RANGE_MLP or BESSEL_RANGE_MLP_TABLE (mlp required; F32 only).
  * Section 2 (Algorithm 3 and Eq. (int)).
  */
 int bessel_logk(int dtype, int64_t n, const void* v, const void* x, void* logk, int nbins,
@@ -105,9 +106,9 @@ int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void* x, const 
  *                   g(t) >= g(t_p) + log eps (a superset, never a subset);
  *   tp[i]           (nullable) peak location t_p (Section 2.2);
  *   logf_peak[i]    (nullable) g at the returned t_p, the shift of Eq. (int);
- *   fallback[i]     (nullable, uint8) with BESSEL_RANGE_MLP: 1 where the learned
- *                   bracket failed its check and the Newton bracket was used.
- * With BESSEL_RANGE_MLP, tp and logf_peak are those of the bracket actually used.
+ *   fallback[i]     (nullable, uint8) with a learned range mode: 1 where the
+ *                   learned bracket failed its check and the Newton bracket was used.
+ * With a learned range mode, tp and logf_peak are those of the bracket actually used.
  */
 int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1,
                  void* tp, void* logf_peak, int range_mode, const bessel_mlp* mlp,
@@ -207,6 +208,15 @@ int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void*
  * 1e-5.  Elements that fail are recomputed by the Newton path in a second
  * kernel on the same stream.
  *
+ * BESSEL_RANGE_MLP_TABLE reads the same network from a table: after each
+ * change of the parameters, the first call in this mode evaluates the
+ * network (the same bf16-MFMA inference) on a 256 x 256 grid of the feature
+ * plane, z in [-4, 4]^2, and stores per cell the bilinear coefficients of
+ * both outputs (2.6 MB, owned by the handle). Each element then interpolates
+ * the outputs of its cell instead of running 128 activations. Features
+ * outside the grid are clamped to its edge. The check and the fallback are
+ * the same as for BESSEL_RANGE_MLP.
+ *
  * Parameter vector (host floats, BESSEL_MLP_NPARAMS): W1 (64 x 2, row-major),
  * b1[64], W2 (64 x 64; W2[i][j] multiplies hidden j of layer 1), b2[64],
  * W3 (2 x 64), b3[2] (BESSEL_MLP_NWEIGHTS trainable values), then
@@ -262,7 +272,8 @@ int bessel_mlp_adam_step(bessel_mlp* mlp, const float* grad, float lr, float bet
                          void* hip_stream);
 /* Raw network outputs y[2 i], y[2 i + 1] for n device inputs; mode 0: FP32 with
  * exact tanh, one element per lane; mode 1: the bf16-MFMA inference of the
- * fused kernel (the same operands and arithmetic). */
+ * fused kernel (the same operands and arithmetic); mode 2: the bilinear table
+ * of BESSEL_RANGE_MLP_TABLE. */
 int bessel_mlp_forward(const bessel_mlp* mlp, int64_t n, const float* v, const float* x, float* y, int mode,
                        void* hip_stream);
 /* Number of elements of the handle's last learned-range call that fell back to

@@ -30,7 +30,7 @@ import ctypes
 import torch
 
 from . import _lib
-from ._lib import F32, F64, RANGE_MLP, RANGE_NEWTON, BesselError, check, load  # noqa: F401
+from ._lib import F32, F64, RANGE_MLP, RANGE_MLP_TABLE, RANGE_NEWTON, BesselError, check, load  # noqa: F401
 
 __all__ = [
     "logk",
@@ -96,7 +96,9 @@ def _range_code(range_: str) -> int:
         return RANGE_NEWTON
     if range_ == "mlp":
         return RANGE_MLP
-    raise ValueError(f"range must be 'newton' or 'mlp', not {range_!r}")
+    if range_ == "mlp_table":
+        return RANGE_MLP_TABLE
+    raise ValueError(f"range must be 'newton', 'mlp' or 'mlp_table', not {range_!r}")
 
 
 def logk(v: torch.Tensor, x: torch.Tensor, nbins: int = 128, range: str = "newton", mlp=None) -> torch.Tensor:

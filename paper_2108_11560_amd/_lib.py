@@ -16,6 +16,7 @@ F32 = 0
 F64 = 1
 RANGE_NEWTON = 0
 RANGE_MLP = 1
+RANGE_MLP_TABLE = 2
 
 STATUS = {
     0: "BESSEL_OK",

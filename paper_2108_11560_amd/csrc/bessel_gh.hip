@@ -110,7 +110,8 @@ extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* 
   (void)mlp;
   if (nsets < 0 || nsamp < 0) return set_error(BESSEL_ERR_ARG, "nsets and nsamp must be >= 0");
   if (range_mode != BESSEL_RANGE_NEWTON)
-    return set_error(range_mode == BESSEL_RANGE_MLP ? BESSEL_ERR_UNSUPPORTED : BESSEL_ERR_RANGE_MODE,
+    return set_error(range_mode == BESSEL_RANGE_MLP || range_mode == BESSEL_RANGE_MLP_TABLE ? BESSEL_ERR_UNSUPPORTED
+                                                                                         : BESSEL_ERR_RANGE_MODE,
                      "the per-set sums use the Newton bracket");
   if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
     return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);

@@ -28,9 +28,10 @@ int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, v
                  hipStream_t st);
 
 // Learned-range paths (bessel_mlp.hip), F32 only.
+// table: the network's bilinear table instead of its per-element inference.
 int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
-             bool grad, const bessel_mlp* mlp, hipStream_t st);
+             bool grad, const bessel_mlp* mlp, bool table, hipStream_t st);
 int range_mlp(int64_t n, const float* v, const float* x, float* t0, float* t1, float* tp, float* gpk,
-              uint8_t* fallback, const bessel_mlp* mlp, hipStream_t st);
+              uint8_t* fallback, const bessel_mlp* mlp, bool table, hipStream_t st);
 
 }  // namespace bk

@@ -361,10 +361,11 @@ static int common_checks(int dtype, int64_t n, const void* v, const void* x, int
   if (dtype != BESSEL_F32 && dtype != BESSEL_F64) return set_error(BESSEL_ERR_DTYPE, "dtype %d is not F32/F64", dtype);
   if (n < 0) return set_error(BESSEL_ERR_ARG, "n = %lld < 0", (long long)n);
   if (n > 0 && (!v || !x)) return set_error(BESSEL_ERR_ARG, "v and x must be non-NULL");
-  if (range_mode != BESSEL_RANGE_NEWTON && range_mode != BESSEL_RANGE_MLP)
+  if (range_mode != BESSEL_RANGE_NEWTON && range_mode != BESSEL_RANGE_MLP && range_mode != BESSEL_RANGE_MLP_TABLE)
     return set_error(BESSEL_ERR_RANGE_MODE, "unknown range_mode %d", range_mode);
-  if (range_mode == BESSEL_RANGE_MLP && !mlp) return set_error(BESSEL_ERR_RANGE_MODE, "range_mode MLP needs an mlp");
-  if (range_mode == BESSEL_RANGE_MLP && dtype != BESSEL_F32)
+  const bool learned = range_mode != BESSEL_RANGE_NEWTON;
+  if (learned && !mlp) return set_error(BESSEL_ERR_RANGE_MODE, "a learned range_mode needs an mlp");
+  if (learned && dtype != BESSEL_F32)
     return set_error(BESSEL_ERR_UNSUPPORTED, "the learned range is provided for F32 only");
   return BESSEL_OK;
 }
@@ -381,8 +382,9 @@ extern "C" int bessel_logk(int dtype, int64_t n, const void* v, const void* x, v
   if (overlaps(logk, nb, v, nb) || overlaps(logk, nb, x, nb))
     return set_error(BESSEL_ERR_ALIAS, "logk overlaps an input");
   hipStream_t st = (hipStream_t)hip_stream;
-  if (range_mode == BESSEL_RANGE_MLP) return logk_mlp(n, (const float*)v, (const float*)x, nullptr, (float*)logk,
-                                                      nullptr, nullptr, nbins, false, mlp, st);
+  if (range_mode != BESSEL_RANGE_NEWTON)
+    return logk_mlp(n, (const float*)v, (const float*)x, nullptr, (float*)logk, nullptr, nullptr, nbins, false, mlp,
+                    range_mode == BESSEL_RANGE_MLP_TABLE, st);
   return logk_newton(dtype, n, v, x, nullptr, logk, nullptr, nullptr, nbins, false, st);
 }
 
@@ -405,9 +407,9 @@ extern "C" int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void
       if (overlaps(outs[a], nb, outs[b], nb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  if (range_mode == BESSEL_RANGE_MLP)
+  if (range_mode != BESSEL_RANGE_NEWTON)
     return logk_mlp(n, (const float*)v, (const float*)x, (const float*)grad_out, (float*)logk, (float*)dv, (float*)dx,
-                    nbins, true, mlp, st);
+                    nbins, true, mlp, range_mode == BESSEL_RANGE_MLP_TABLE, st);
   return logk_newton(dtype, n, v, x, grad_out, logk, dv, dx, nbins, true, st);
 }
 
@@ -459,9 +461,9 @@ extern "C" int bessel_range(int dtype, int64_t n, const void* v, const void* x, 
       return set_error(BESSEL_ERR_ALIAS, "fallback overlaps an output");
   }
   hipStream_t st = (hipStream_t)hip_stream;
-  if (range_mode == BESSEL_RANGE_MLP)
+  if (range_mode != BESSEL_RANGE_NEWTON)
     return range_mlp(n, (const float*)v, (const float*)x, (float*)t0, (float*)t1, (float*)tp, (float*)logf_peak,
-                     fallback, mlp, st);
+                     fallback, mlp, range_mode == BESSEL_RANGE_MLP_TABLE, st);
   return range_newton(dtype, n, v, x, t0, t1, tp, logf_peak, st);
 }
 

@@ -458,6 +458,71 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __rest
   }
 }
 
+// Tabulated network (range mode BESSEL_RANGE_MLP_TABLE).  The features are
+// two-dimensional, so the network's outputs can be tabulated once per change
+// of the parameters: k_mlp_tab_nodes runs the bf16-MFMA inference above on a
+// kTab x kTab grid of the feature plane, z in [-kTabZ, kTabZ]^2, and
+// k_mlp_tab_cells stores per cell the bilinear coefficients of both outputs
+// (value, d/du, d/dw, d2/dudw; 8 floats = one aligned 32-byte record).  An
+// element then costs one record load and six FMAs instead of 128 activations.
+// Interpolation moves the outputs by ~1e-3 (y0) and ~4e-4 (y1) on the scale
+// workload, far inside the margins; the check after the bins still decides.
+constexpr int kTab = 256;
+constexpr float kTabZ = 4.0f;
+constexpr int kCells = kTab - 1;
+
+// grid: kTab * kTab / kBlock blocks (every lane a node; the whole wavefront
+// takes part in the MFMAs)
+__global__ __launch_bounds__(kBlock) void k_mlp_tab_nodes(const float* __restrict__ Q, float* __restrict__ nodes) {
+  const int g = blockIdx.x * kBlock + threadIdx.x;
+  const int i = g / kTab, j = g - i * kTab;
+  const float step = 2.0f * kTabZ / (float)(kTab - 1);
+  float y0, y1;
+  mlp_wave_mfma(Q, fmaf(step, (float)i, -kTabZ), fmaf(step, (float)j, -kTabZ), y0, y1);
+  nodes[2 * g] = y0;
+  nodes[2 * g + 1] = y1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_tab_cells(const float* __restrict__ nodes, float4* __restrict__ cells) {
+  const int c = blockIdx.x * kBlock + threadIdx.x;
+  if (c >= kCells * kCells) return;
+  const int i = c / kCells, j = c - i * kCells;
+  const float* a = nodes + 2 * (i * kTab + j);  // (i, j)
+  const float* b = a + 2;                       // (i, j + 1)
+  const float* d = a + 2 * kTab;                // (i + 1, j)
+  const float* e = d + 2;                       // (i + 1, j + 1)
+  cells[2 * c] = make_float4(a[0], d[0] - a[0], b[0] - a[0], (e[0] - d[0]) - (b[0] - a[0]));
+  cells[2 * c + 1] = make_float4(a[1], d[1] - a[1], b[1] - a[1], (e[1] - d[1]) - (b[1] - a[1]));
+}
+
+// Bilinear lookup; features outside the table are clamped to its edge (their
+// brackets are then usually rejected by the check and recomputed).
+__device__ __forceinline__ void mlp_table(const float4* __restrict__ cells, float z0, float z1, float& y0,
+                                          float& y1) {
+  const float s = (float)(kTab - 1) / (2.0f * kTabZ);
+  const float u = fminf(fmaxf((z0 + kTabZ) * s, 0.0f), (float)kCells - 1e-3f);
+  const float w = fminf(fmaxf((z1 + kTabZ) * s, 0.0f), (float)kCells - 1e-3f);
+  const int i = (int)u, j = (int)w;
+  const float fu = u - (float)i, fw = w - (float)j;
+  const float4 r0 = cells[2 * (i * kCells + j)];
+  const float4 r1 = cells[2 * (i * kCells + j) + 1];
+  y0 = fmaf(fw, fmaf(fu, r0.w, r0.z), fmaf(fu, r0.y, r0.x));
+  y1 = fmaf(fw, fmaf(fu, r1.w, r1.z), fmaf(fu, r1.y, r1.x));
+}
+
+__global__ __launch_bounds__(kBlock) void k_mlp_forward_table(const float* __restrict__ Q,
+                                                              const float4* __restrict__ cells, int64_t n,
+                                                              const float* __restrict__ v,
+                                                              const float* __restrict__ x, float* __restrict__ y) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  float z0, z1, y0, y1;
+  mlp_features_q(Q, v[i], x[i], z0, z1);
+  mlp_table(cells, z0, z1, y0, y1);
+  y[2 * i] = y0;
+  y[2 * i + 1] = y1;
+}
+
 // g at one point for the shift of a learned bracket, FP32 hardware form.  Any finite shift is exact (log K = G + log(h S0) with S0 relative to
 // the same G); inside the bracket g >= max g - L, so the exponents stay below
 // L and FP32 cannot overflow.
@@ -479,10 +544,12 @@ __device__ __forceinline__ bool accept_bins(const BinSums& s, float t0) {
   return cover && resolved && isfinite(s.S0) && s.S0 > 0.0;
 }
 
-// Fused: network (bf16 MFMA) -> bracket -> checked FP32 bins -> outputs, or the
-// element index onto the worklist (count at work[0], indices from work[1]).
-template <bool GRAD, int NB>
-__global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q, int64_t n, int nbins,
+// Fused: network (bf16 MFMA, or its table with TAB) -> bracket -> checked FP32
+// bins -> outputs, or the element index onto the worklist (count at work[0],
+// indices from work[1]).
+template <bool GRAD, int NB, bool TAB>
+__global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q, const float4* __restrict__ cells,
+                                                     int64_t n, int nbins,
                                                      const float* __restrict__ vin, const float* __restrict__ xin,
                                                      const float* __restrict__ gout, float* __restrict__ logk,
                                                      float* __restrict__ dv, float* __restrict__ dx,
@@ -500,7 +567,8 @@ __global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q
   float z0 = 0.0f, z1 = 0.0f;
   if (in && !special) mlp_features_q(Q, vs, xf, z0, z1);
   float y0, y1;
-  mlp_wave_mfma(Q, z0, z1, y0, y1);
+  if constexpr (TAB) mlp_table(cells, z0, z1, y0, y1);
+  else mlp_wave_mfma(Q, z0, z1, y0, y1);
   bool ok = true;
   float t0 = 0.0f, t1 = 0.0f, G = 0.0f;
   if (in && !special) {
@@ -614,6 +682,11 @@ struct bessel_mlp {
   float* params = nullptr;  // [kNP]
   float* packed = nullptr;  // [kNQ] inference operands derived from params
   bool packed_stale = true; // params changed since the last k_mlp_pack
+  float* tab_nodes = nullptr;     // [2 kTab^2] network outputs on the grid (range mode table)
+  int64_t cap_tab_nodes = 0;
+  float4* tab_cells = nullptr;    // [2 kCells^2] bilinear records
+  int64_t cap_tab_cells = 0;
+  bool table_stale = true;  // packed operands rebuilt since the table was
   float* adam_m = nullptr;  // [kNW]
   float* adam_s = nullptr;  // [kNW]
   float* grad = nullptr;    // [kNW + 1] (last: loss)
@@ -694,7 +767,7 @@ extern "C" int bessel_mlp_destroy(bessel_mlp* m) {
   void* sync_ptrs[] = {m->params, m->packed, m->adam_m, m->adam_s, m->grad};
   for (void* p : sync_ptrs)
     if (p) (void)hipFree(p);
-  void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work};  // from hipMallocAsync
+  void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work, m->tab_nodes, m->tab_cells};  // hipMallocAsync
   for (void* p : async_ptrs)
     if (p) (void)hipFreeAsync(p, nullptr);
   (void)hipDeviceSynchronize();
@@ -821,14 +894,36 @@ static int refresh_packed(const bessel_mlp* mc, hipStream_t st) {
   if (!m->packed_stale) return BESSEL_OK;
   k_mlp_pack<<<1, kBlock, 0, st>>>(m->params, m->packed);
   const int rc = check_launch("k_mlp_pack");
-  if (rc == BESSEL_OK) m->packed_stale = false;
+  if (rc == BESSEL_OK) {
+    m->packed_stale = false;
+    m->table_stale = true;
+  }
+  return rc;
+}
+
+// Rebuild the network's table (after the operands) on the caller's stream if
+// the operands changed since it was last built.
+static int refresh_table(const bessel_mlp* mc, hipStream_t st) {
+  bessel_mlp* m = const_cast<bessel_mlp*>(mc);
+  int rc = refresh_packed(m, st);
+  if (rc || !m->table_stale) return rc;
+  rc = ensure(m->tab_nodes, m->cap_tab_nodes, (int64_t)2 * kTab * kTab, st, "network table");
+  if (rc == BESSEL_OK) rc = ensure(m->tab_cells, m->cap_tab_cells, (int64_t)2 * kCells * kCells, st, "network table");
+  if (rc) return rc;
+  static_assert((kTab * kTab) % kBlock == 0, "the node grid fills whole blocks");
+  k_mlp_tab_nodes<<<kTab * kTab / kBlock, kBlock, 0, st>>>(m->packed, m->tab_nodes);
+  rc = check_launch("k_mlp_tab_nodes");
+  if (rc) return rc;
+  k_mlp_tab_cells<<<(kCells * kCells + kBlock - 1) / kBlock, kBlock, 0, st>>>(m->tab_nodes, m->tab_cells);
+  rc = check_launch("k_mlp_tab_cells");
+  if (rc == BESSEL_OK) m->table_stale = false;
   return rc;
 }
 
 extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v, const float* x, float* y, int mode,
                                   void* hip_stream) {
   if (!m || (n > 0 && (!v || !x || !y))) return set_error(BESSEL_ERR_ARG, "NULL argument");
-  if (mode != 0 && mode != 1) return set_error(BESSEL_ERR_ARG, "mode must be 0 (FP32) or 1 (bf16 MFMA)");
+  if (mode < 0 || mode > 2) return set_error(BESSEL_ERR_ARG, "mode must be 0 (FP32), 1 (bf16 MFMA) or 2 (table)");
   if (n == 0) return BESSEL_OK;
   dim3 grid;
   int rc = grid_for(n, grid);
@@ -836,10 +931,14 @@ extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v
   hipStream_t st = (hipStream_t)hip_stream;
   if (mode == 0) {
     k_mlp_forward_f32<<<grid, kBlock, 0, st>>>(m->params, n, v, x, y);
-  } else {
+  } else if (mode == 1) {
     rc = refresh_packed(m, st);
     if (rc) return rc;
     k_mlp_forward_mfma<<<grid, kBlock, 0, st>>>(m->packed, n, v, x, y);
+  } else {
+    rc = refresh_table(m, st);
+    if (rc) return rc;
+    k_mlp_forward_table<<<grid, kBlock, 0, st>>>(m->packed, m->tab_cells, n, v, x, y);
   }
   return check_launch("k_mlp_forward");
 }
@@ -847,10 +946,35 @@ extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v
 namespace bk {
 
 // Fused learned-range pass + fallback (shared by logk, logk_dv_dx and range).
+template <bool GRAD, bool TAB>
+static void launch_fused(dim3 grid, hipStream_t st, const bessel_mlp* m, int64_t n, int nbins, const float* v,
+                         const float* x, const float* go, float* lk, float* dv, float* dx, float* t0, float* t1,
+                         float* tp, float* gp, uint8_t* fb) {
+  const float4* cells = TAB ? m->tab_cells : nullptr;
+  switch (nbins) {
+    case 64:
+      k_logk_mlp<GRAD, 64, TAB><<<grid, kBlock, 0, st>>>(m->packed, cells, n, nbins, v, x, go, lk, dv, dx, t0, t1,
+                                                         tp, gp, fb, m->work);
+      break;
+    case 128:
+      k_logk_mlp<GRAD, 128, TAB><<<grid, kBlock, 0, st>>>(m->packed, cells, n, nbins, v, x, go, lk, dv, dx, t0, t1,
+                                                          tp, gp, fb, m->work);
+      break;
+    case 256:
+      k_logk_mlp<GRAD, 256, TAB><<<grid, kBlock, 0, st>>>(m->packed, cells, n, nbins, v, x, go, lk, dv, dx, t0, t1,
+                                                          tp, gp, fb, m->work);
+      break;
+    default:
+      k_logk_mlp<GRAD, 0, TAB><<<grid, kBlock, 0, st>>>(m->packed, cells, n, nbins, v, x, go, lk, dv, dx, t0, t1,
+                                                        tp, gp, fb, m->work);
+      break;
+  }
+}
+
 template <bool GRAD>
 static int run_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx,
                    float* t0, float* t1, float* tp, float* gp, uint8_t* fb, int nbins, const bessel_mlp* mc,
-                   hipStream_t st) {
+                   bool table, hipStream_t st) {
   bessel_mlp* m = const_cast<bessel_mlp*>(mc);
   dim3 grid;
   int rc = grid_for(n, grid);
@@ -858,27 +982,13 @@ static int run_mlp(int64_t n, const float* v, const float* x, const float* go, f
   if (n > 0x7fffffffLL - 1) return set_error(BESSEL_ERR_ARG, "n too large for the learned-range worklist");
   rc = ensure(m->work, m->cap_work, n + 1, st, "worklist");
   if (rc) return rc;
-  rc = refresh_packed(m, st);
+  rc = table ? refresh_table(m, st) : refresh_packed(m, st);
   if (rc) return rc;
   k_zero_int<<<1, 1, 0, st>>>(m->work);
-  switch (nbins) {
-    case 64:
-      k_logk_mlp<GRAD, 64><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
-                                                    m->work);
-      break;
-    case 128:
-      k_logk_mlp<GRAD, 128><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
-                                                     m->work);
-      break;
-    case 256:
-      k_logk_mlp<GRAD, 256><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
-                                                     m->work);
-      break;
-    default:
-      k_logk_mlp<GRAD, 0><<<grid, kBlock, 0, st>>>(m->packed, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb,
-                                                   m->work);
-      break;
-  }
+  if (table)
+    launch_fused<GRAD, true>(grid, st, m, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb);
+  else
+    launch_fused<GRAD, false>(grid, st, m, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb);
   rc = check_launch("k_logk_mlp");
   if (rc) return rc;
   // persistent fallback grid: 4 blocks per CU
@@ -901,15 +1011,16 @@ static int run_mlp(int64_t n, const float* v, const float* x, const float* go, f
 }
 
 int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
-             bool grad, const bessel_mlp* mlp, hipStream_t st) {
-  if (grad) return run_mlp<true>(n, v, x, go, lk, dv, dx, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp, st);
+             bool grad, const bessel_mlp* mlp, bool table, hipStream_t st) {
+  if (grad)
+    return run_mlp<true>(n, v, x, go, lk, dv, dx, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp, table, st);
   return run_mlp<false>(n, v, x, nullptr, lk, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp,
-                        st);
+                        table, st);
 }
 
 int range_mlp(int64_t n, const float* v, const float* x, float* t0, float* t1, float* tp, float* gpk,
-              uint8_t* fallback, const bessel_mlp* mlp, hipStream_t st) {
-  return run_mlp<false>(n, v, x, nullptr, nullptr, nullptr, nullptr, t0, t1, tp, gpk, fallback, 128, mlp, st);
+              uint8_t* fallback, const bessel_mlp* mlp, bool table, hipStream_t st) {
+  return run_mlp<false>(n, v, x, nullptr, nullptr, nullptr, nullptr, t0, t1, tp, gpk, fallback, 128, mlp, table, st);
 }
 
 }  // namespace bk

@@ -176,16 +176,16 @@ class RangeMLP:
 
 def calibrate_margins(mlp: RangeMLP, v: torch.Tensor, x: torch.Tensor, target_fallback: float = 0.005,
                       grid_t1=(0.0, 0.01, 0.02, 0.04, 0.07, 0.1, 0.15, 0.2, 0.3),
-                      grid_t0=(0.0, 0.01, 0.02, 0.04, 0.07, 0.1)):
+                      grid_t0=(0.0, 0.01, 0.02, 0.04, 0.07, 0.1), range: str = "mlp"):
     """Smallest (margin_t1, margin_t0) on the grid whose fallback rate on (v, x)
-    is at most target_fallback (by the library's own check); returns
-    (margin_t1, margin_t0, rate)."""
+    is at most target_fallback (by the library's own check, in the learned
+    range mode ``range``: "mlp" or "mlp_table"); returns (margin_t1, margin_t0, rate)."""
     from . import bessel_range
     best = None
     for m1 in grid_t1:
         for m0 in grid_t0:
             mlp.set_margins(m1, m0)
-            *_, fb = bessel_range(v, x, range="mlp", mlp=mlp, want_fallback=True)
+            *_, fb = bessel_range(v, x, range=range, mlp=mlp, want_fallback=True)
             rate = float(fb.float().mean())
             if rate <= target_fallback:
                 if best is None or m1 + m0 < best[0] + best[1]:
@@ -194,7 +194,7 @@ def calibrate_margins(mlp: RangeMLP, v: torch.Tensor, x: torch.Tensor, target_fa
     if best is None:
         m1, m0 = grid_t1[-1], grid_t0[-1]
         mlp.set_margins(m1, m0)
-        *_, fb = bessel_range(v, x, range="mlp", mlp=mlp, want_fallback=True)
+        *_, fb = bessel_range(v, x, range=range, mlp=mlp, want_fallback=True)
         best = (m1, m0, float(fb.float().mean()))
     mlp.set_margins(best[0], best[1])
     return best

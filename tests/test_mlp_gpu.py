@@ -302,3 +302,129 @@ def test_learned_range_gain(mods, trained):
     # against the plain FP64 method, at the FP32 error bar
     assert rate["mlp_fwd"] >= 1.2 * rate["f64_fwd"]
     assert rate["mlp_fwd_bwd"] >= 1.1 * rate["f64_fwd_bwd"]
+
+
+# ---- the network read from its bilinear table (range="mlp_table") ----------
+
+
+def test_table_outputs_follow_the_network(mods, trained):
+    # the table holds the bf16-MFMA network at its grid nodes; against the FP32
+    # network (exact tanh) it is about as close as the per-element bf16
+    # inference itself (whose rounding noise, ~1e-2 here, dominates the
+    # interpolation error of ~1e-3)
+    bk, M = mods
+    mlp, _ = trained
+    v, x, _ = workloads.scale_pairs(1 << 16, seed=406)
+    vt, xt = dev32(v), dev32(x)
+    y32 = host(mlp.forward(vt, xt, mode=0))
+    d_net = np.abs(host(mlp.forward(vt, xt, mode=1)) - y32).max(axis=0)
+    d_tab = np.abs(host(mlp.forward(vt, xt, mode=2)) - y32).max(axis=0)
+    print("max |bf16 network - FP32|: y0 %.2e, y1 %.2e;  max |table - FP32|: y0 %.2e, y1 %.2e"
+          % (*d_net, *d_tab))
+    scale = max(1.0, float(np.abs(y32).max()))
+    assert d_tab.max() <= 3e-2 * scale
+    assert np.all(d_tab <= 2.0 * d_net + 2e-3)
+
+
+def test_table_follows_parameter_changes(mods, trained):
+    bk, M = mods
+    mlp, _ = trained
+    again = M.RangeMLP(mlp.params())
+    v, x, _ = workloads.scale_pairs(4096, seed=407)
+    vt, xt = dev32(v), dev32(x)
+    before = host(again.forward(vt, xt, mode=2))
+    p = mlp.params().copy()
+    p[R.NPARAMS - 2:R.NPARAMS] += np.float32(0.25)  # shift the output biases b3
+    again.set_params(p)
+    after = host(again.forward(vt, xt, mode=2))
+    assert np.allclose(after - before, 0.25, atol=1e-5)
+    again.close()
+
+
+@pytest.mark.parametrize("nbins", [64, 128])
+def test_table_range_parity(mods, trained, nbins):
+    bk, M = mods
+    mlp, _ = trained
+    v, x, strata = workloads.scale_pairs(1 << 20, seed=1)
+    idx = workloads.stratified_subset(strata, 1 << 13, seed=11)
+    vt, xt = dev32(v), dev32(x)
+    lk = bk.logk(vt, xt, nbins=nbins, range="mlp_table", mlp=mlp)
+    n_fb = mlp.fallback_count()
+    print("table fallback rate", n_fb / v.size)
+    assert n_fb <= 0.02 * v.size
+    ref = oracle.logk(host(vt)[idx], host(xt)[idx])
+    assert (np.abs(host(lk)[idx] - ref) / np.maximum(1.0, np.abs(ref))).max() <= 1e-5
+    ref64 = bk.logk(vt.double(), xt.double(), nbins=nbins)
+    assert float(((lk.double() - ref64).abs() / ref64.abs().clamp_min(1.0)).max()) <= 1e-5
+    go = dev32(workloads.upstream_grad(v.size, seed=13))
+    l2, dv, dx = bk.logk_dv_dx(vt, xt, grad_out=go, nbins=nbins, range="mlp_table", mlp=mlp)
+    _, rdv, rdx = oracle.logk(host(vt)[idx], host(xt)[idx], deriv=True)
+    g = host(go)[idx]
+    assert (np.abs(host(dv)[idx] - g * rdv) / np.maximum(1.0, np.abs(g * rdv))).max() <= 1e-5
+    assert (np.abs(host(dx)[idx] - g * rdx) / np.maximum(1.0, np.abs(g * rdx))).max() <= 1e-5
+    assert float(((l2.double() - ref64).abs() / ref64.abs().clamp_min(1.0)).max()) <= 1e-5
+
+
+def test_table_brackets_contain_exact_set(mods, trained):
+    bk, M = mods
+    mlp, _ = trained
+    v, x, _ = workloads.scale_pairs(1 << 14, seed=408)
+    vt, xt = dev32(v), dev32(x)
+    t0, t1, tp, G, fb = bk.bessel_range(vt, xt, range="mlp_table", mlp=mlp, want_fallback=True)
+    fb = host(fb).astype(bool)
+    assert mlp.fallback_count() == int(fb.sum())
+    _, _, e0, e1 = oracle.range_exact(host(vt), host(xt), LOG_EPS32)
+    t0, t1 = host(t0), host(t1)
+    assert np.all(t0 <= e0 + 1e-6 * (1 + e0))
+    assert np.all(t1 >= e1 - 1e-6 * (1 + e1))
+    n0, n1, _, _ = bk.bessel_range(vt, xt)
+    assert np.array_equal(t0[fb], host(n0)[fb]) and np.array_equal(t1[fb], host(n1)[fb])
+
+
+def test_table_forced_fallback_is_bitwise_newton(mods):
+    bk, M = mods
+    v, x, _ = workloads.scale_pairs(5000, seed=409)
+    vt, xt = dev32(v), dev32(x)
+    prev = bk.set_split_threshold(0)
+    try:
+        newton = bk.logk(vt, xt, nbins=128)
+        nl, ndv, ndx = bk.logk_dv_dx(vt, xt, nbins=128)
+    finally:
+        bk.set_split_threshold(prev)
+    p = np.zeros(M.NPARAMS, dtype=np.float32)
+    p[M.O_META:M.O_META + 6] = [1.0, 3.0, 0.0, 4.0, -30.0, 0.0]
+    mlp = M.RangeMLP(p)
+    out = bk.logk(vt, xt, nbins=128, range="mlp_table", mlp=mlp)
+    assert mlp.fallback_count() == v.size
+    assert torch.equal(out, newton)
+    l2, dv, dx = bk.logk_dv_dx(vt, xt, nbins=128, range="mlp_table", mlp=mlp)
+    assert torch.equal(dv, ndv) and torch.equal(dx, ndx) and torch.equal(l2, nl)
+    mlp.close()
+
+
+def test_table_gain(mods, trained):
+    """The network read from its table against per-element inference, the
+    FP32 Newton bracket and the FP64 method (2^22 scale pairs, 128 bins)."""
+    bk, M = mods
+    mlp, _ = trained
+    n = 1 << 22
+    v, x, _ = workloads.scale_pairs(n, seed=23)
+    v32, x32 = dev32(v), dev32(x)
+    v64, x64 = v32.double(), x32.double()
+    go32 = dev32(workloads.upstream_grad(n, seed=24))
+    rate = {
+        "table_fwd": _evals_per_s(lambda: bk.logk(v32, x32, range="mlp_table", mlp=mlp), n),
+        "mlp_fwd": _evals_per_s(lambda: bk.logk(v32, x32, range="mlp", mlp=mlp), n),
+        "newton32_fwd": _evals_per_s(lambda: bk.logk(v32, x32), n),
+        "f64_fwd": _evals_per_s(lambda: bk.logk(v64, x64), n),
+        "table_fwd_bwd": _evals_per_s(lambda: bk.logk_dv_dx(v32, x32, grad_out=go32, range="mlp_table", mlp=mlp), n),
+        "newton32_fwd_bwd": _evals_per_s(lambda: bk.logk_dv_dx(v32, x32, grad_out=go32), n),
+    }
+    fallback = mlp.fallback_count() / n
+    print({k: f"{r:.3e}" for k, r in rate.items()}, "fallback", fallback)
+    print("table / FP32 Newton: fwd %.2fx, fwd+bwd %.2fx;  table / per-element network fwd %.2fx" % (
+        rate["table_fwd"] / rate["newton32_fwd"], rate["table_fwd_bwd"] / rate["newton32_fwd_bwd"],
+        rate["table_fwd"] / rate["mlp_fwd"]))
+    assert fallback <= 0.02
+    assert rate["table_fwd"] >= 1.2 * rate["f64_fwd"]
+    assert rate["table_fwd"] > rate["mlp_fwd"]
