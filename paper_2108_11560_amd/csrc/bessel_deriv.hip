@@ -36,13 +36,15 @@ namespace {
 // Past this t the factor x cosh t exceeds every level the searches compare
 // against for any x >= 1e-36 (x cosh 700 > 1e267): g_ab is taken as -inf.
 constexpr double kDkTMax = 700.0;
-// bisection steps in log t for the peak, then safeguarded Newton steps
-constexpr int kDkPeakBisect = 14;
-constexpr int kDkPeakNewton = 3;
+// bisection steps in log t for the peak, then safeguarded Newton steps (the
+// peak only sets the shift and the start of the end searches: any point near
+// it gives a valid bracket)
+constexpr int kDkPeakBisect = 8;
+constexpr int kDkPeakNewton = 4;
 // each end: at most kDkDoubling doublings of the step, then kDkRefine rounds
 // of one bisection and one safeguarded Newton step
 constexpr int kDkDoubling = 64;
-constexpr int kDkRefine = 5;
+constexpr int kDkRefine = 3;
 
 struct GabAt {
   double g;   // g_ab(t)
@@ -82,8 +84,20 @@ __device__ __forceinline__ GabAt gab_at(double v, double x, int a, int b, double
   const double rch = rcp_f64(ch);
   o.g1 = (double)a * rt + (double)b * sh * rch + v * num * rden - x * sh;
   if (VAL) {
-    double g = (double)b * (t - kLn2 + log_f64(1.0 + Ei * Ei)) + (v * t - kLn2 + log_f64(den)) - x * ch;
-    if (a) g += (double)a * log_f64(t);
+    // a log t + b log cosh t = b (t - log 2) + log(t^a (1 + e^{-2t})^b): one
+    // log for both while the product is a normal number ((1 + e^{-2t})^b <= 2^8
+    // and t <= 700 bound it above; a tiny t^a takes the two logs apart)
+    double pw = 1.0;
+    for (int k = 0; k < a; ++k) pw *= t;
+    const double c2 = 1.0 + Ei * Ei;
+    for (int k = 0; k < b; ++k) pw *= c2;
+    double g = (v * t - kLn2 + log_f64(den)) - x * ch;
+    if (b) g = fma((double)b, t - kLn2, g);
+    if (pw >= 1e-290) {
+      if (a || b) g += log_f64(pw);
+    } else {
+      g += (double)a * log_f64(t) + (double)b * log_f64(c2);
+    }
     o.g = g;
   }
   if (D2) {
