@@ -5,7 +5,8 @@
  *
  *   K_{1/2}(x) = sqrt(pi / (2x)) e^{-x}   (DLMF 10.39.2), so
  *   log K_{1/2}(x) = 0.5 log(pi / (2x)) - x,  d/dx log K = -1/(2x) - 1,
- *   d2/dx2 log K = 1 / (2 x^2).
+ *   d2/dx2 log K = 1 / (2 x^2),
+ *   d2K/dx2 = sqrt(pi / 2) e^{-x} (x^{-1/2} + x^{-3/2} + (3/4) x^{-5/2}).
  *
  * Prints one line per check and exits non-zero if any check fails.
  */
@@ -85,6 +86,27 @@ int main(void) {
   check(e1 <= 1e-12, "bessel_logk_hess, d/dx log K_{1/2}", e1);
   check(e2 <= 1e-10, "bessel_logk_hess, d2/dx2 log K_{1/2}", e2);
 
+  /* d2K/dx2 itself, its integrand over its own bracket, as log |D| and sign */
+  double *ld = NULL, *sg = NULL, hld[N], hsg[N];
+  if (!hip_ok(hipMalloc((void**)&ld, bytes), "hipMalloc") || !hip_ok(hipMalloc((void**)&sg, bytes), "hipMalloc"))
+    return 2;
+  rc = bessel_logdk(BESSEL_F64, N, v, x, 0, 2, ld, sg, 128, NULL);
+  if (rc != BESSEL_OK || !hip_ok(hipMemcpy(hld, ld, bytes, hipMemcpyDeviceToHost), "copy") ||
+      !hip_ok(hipMemcpy(hsg, sg, bytes, hipMemcpyDeviceToHost), "copy")) {
+    fprintf(stderr, "bessel_logdk: %d %s\n", rc, bessel_last_error());
+    return 1;
+  }
+  double e3 = 0.0;
+  int signs_ok = 1;
+  for (int i = 0; i < N; ++i) {
+    const double xi = hx[i];
+    const double ref = 0.5 * log(kPi / 2.0) - xi + log(pow(xi, -0.5) + pow(xi, -1.5) + 0.75 * pow(xi, -2.5));
+    const double m = fabs(hld[i] - ref) / fmax(1.0, fabs(ref));
+    if (m > e3) e3 = m;
+    if (hsg[i] != 1.0) signs_ok = 0;
+  }
+  check(e3 <= 1e-12 && signs_ok, "bessel_logdk, log d2K/dx2 of K_{1/2}", e3);
+
   /* an invalid argument comes back as a status with a message, before any GPU work */
   rc = bessel_logk(BESSEL_F64, N, v, x, lk, 1, BESSEL_RANGE_NEWTON, NULL, NULL);
   check(rc == BESSEL_ERR_NBINS, "nbins = 1 rejected with BESSEL_ERR_NBINS", 0.0);
@@ -96,5 +118,7 @@ int main(void) {
   (void)hipFree(dv);
   (void)hipFree(dx);
   (void)hipFree(dxx);
+  (void)hipFree(ld);
+  (void)hipFree(sg);
   return failures ? 1 : 0;
 }

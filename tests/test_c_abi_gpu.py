@@ -1,7 +1,8 @@
 """The C ABI used from plain C with no Python in the loop: the example
 program (examples/c_abi_demo.c, built with the library) runs as a child
-process and checks log K_{1/2}, its first and second x-derivatives against
-the closed form (DLMF 10.39.2) and the error path of an invalid nbins."""
+process and checks log K_{1/2}, its first and second x-derivatives and the
+second x-derivative of K itself (bessel_logdk) against the closed form
+(DLMF 10.39.2), and the error path of an invalid nbins."""
 
 import os
 import subprocess
@@ -20,4 +21,4 @@ def test_c_program():
     r = subprocess.run([EXE], capture_output=True, text=True, timeout=120)
     print(r.stdout)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count(" ok ") == 4
+    assert r.stdout.count(" ok ") == 5
