@@ -224,13 +224,14 @@ def test_forced_fallback_is_bitwise_newton(mods):
     mlp.close()
 
 
-def test_learned_range_domain_conventions(mods, trained):
+@pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
+def test_learned_range_domain_conventions(mods, trained, mode):
     bk, M = mods
     mlp, _ = trained
     nan, inf = float("nan"), float("inf")
     v = dev32([nan, 1.0, 1.0, 1.0, 1.0, inf, 2.5, -2.5])
     x = dev32([1.0, nan, -1.0, 0.0, inf, 2.0, 3.0, 3.0])
-    lk = host(bk.logk(v, x, range="mlp", mlp=mlp))
+    lk = host(bk.logk(v, x, range=mode, mlp=mlp))
     assert np.isnan(lk[:3]).all()
     assert lk[3] == np.inf and lk[4] == -np.inf and lk[5] == np.inf
     assert lk[6] == lk[7]
