@@ -82,8 +82,12 @@ def test_nbins_range(lib, nbins):
 
 def test_range_mode(lib):
     assert lib.bessel_logk(1, 4, FAKE_A, FAKE_B, FAKE_C, 128, 9, NULL, NULL) == -4
-    # the learned range needs a predictor handle
+    # the learned range (per element or tabulated) needs a predictor handle
     assert lib.bessel_logk(0, 4, FAKE_A, FAKE_B, FAKE_C, 128, 1, NULL, NULL) == -4
+    assert lib.bessel_logk(0, 4, FAKE_A, FAKE_B, FAKE_C, 128, 2, NULL, NULL) == -4
+    # ... and is provided for F32 only
+    assert lib.bessel_logk(1, 4, FAKE_A, FAKE_B, FAKE_C, 128, 2, FAKE_A, NULL) == -7
+    assert lib.bessel_range(1, 4, FAKE_A, FAKE_B, FAKE_C, NULL, NULL, NULL, 2, FAKE_A, NULL, NULL) == -7
 
 
 def test_zero_length_is_noop(lib):
@@ -112,6 +116,7 @@ def test_error_status_names():
 def test_gh_argument_errors(lib):
     args = [FAKE_A, FAKE_A, FAKE_A, FAKE_A, 4, FAKE_B, NULL, FAKE_C, NULL, NULL, NULL, NULL]
     assert lib.bessel_gh_logk_sum(4, *args, 128, 1, NULL, NULL) == -7  # learned range: unsupported here
+    assert lib.bessel_gh_logk_sum(4, *args, 128, 2, NULL, NULL) == -7
     assert lib.bessel_gh_logk_sum(4, *args, 1, 0, NULL, NULL) == -3
     assert lib.bessel_gh_logk_sum(-1, *args, 128, 0, NULL, NULL) == -1
     assert lib.bessel_gh_logk_sum(0, *args, 128, 0, NULL, NULL) == 0
