@@ -117,6 +117,25 @@ def test_training_reduces_loss(mods):
     mlp.close()
 
 
+def test_training_is_deterministic(mods):
+    # minibatches from splitmix64 of (seed, step, sample), gradients reduced over
+    # blocks in a fixed order: the same seed gives bitwise the same parameters
+    bk, M = mods
+    v, x, _ = workloads.scale_pairs(1 << 14, seed=9)
+    runs = []
+    for _ in range(2):
+        mlp = M.RangeMLP(M.glorot_params(5))
+        losses = mlp.train(dev32(v), dev32(x), steps=300, batch=2048, lr=3e-3, lr_final=1e-3, seed=3)
+        runs.append((mlp.params(), losses))
+        mlp.close()
+    assert np.array_equal(runs[0][0], runs[1][0])
+    assert np.array_equal(runs[0][1], runs[1][1])
+    other = M.RangeMLP(M.glorot_params(5))
+    other.train(dev32(v), dev32(x), steps=300, batch=2048, lr=3e-3, lr_final=1e-3, seed=4)
+    assert not np.array_equal(other.params(), runs[0][0])
+    other.close()
+
+
 @pytest.fixture(scope="module")
 def trained(mods):
     bk, M = mods
