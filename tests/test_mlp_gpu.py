@@ -361,7 +361,7 @@ def test_table_follows_parameter_changes(mods, trained):
     again.close()
 
 
-@pytest.mark.parametrize("nbins", [64, 128])
+@pytest.mark.parametrize("nbins", [64, 128, 256, 100])  # 100: the runtime bin count
 def test_table_range_parity(mods, trained, nbins):
     bk, M = mods
     mlp, _ = trained
