@@ -46,9 +46,14 @@ import workloads  # noqa: E402
 # Algorithmic VALU work per element, in lane-slots (one full-rate VALU
 # instruction on one lane = 1 slot; an FP32 transcendental = 2, measured half
 # rate; v_rcp_f64 = 4):  W(n) = (n + 1) * W_NODE + W_PRE, from the operation
-# count of the formulation (one table per path in DESIGN.md, "Roofline").
-# keyed by (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2 with the
-# second derivatives too
+# count of the formulation.  Per FP32 node: argument 1, conversion 1, exp2 2,
+# widening 1, sum 1, u 1, linear part 1, cosh recurrence 1 (= 9); with d/dv and
+# d/dx + r, t, w r, w u and two sums (= 15); second derivatives + 6 (= 21).
+# Per FP64 node: t 1, cosh 1, argument 2, exp 15, sum 1, u 1, e^{+-t} 2,
+# re-anchoring 1.5 (= 24.5), + 6 with d/dv and d/dx, + 6 more for the second
+# derivatives.  W_PRE: peak 120, G 80, t1 50, t0 60, bin set-up 120, final log
+# and reciprocal 50, loads 20.  Keyed by (dtype, derivative order): 0 log K,
+# 1 with d/dv and d/dx, 2 with the second derivatives too.
 W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
           ("f64", 0): 24.5, ("f64", 1): 30.5, ("f64", 2): 36.5}
 W_PRE = 500.0
@@ -72,7 +77,7 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the two
 # kernels are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "1dbf0d5992a4f3e6a72e06a7d8fc4165b471611bb9c78cbba3b0e1b45fed4474",
+TRAFFIC = {"sources_sha256": "2708df36f47a3d368fe27a9d8df2761540fad0b906052c43b03e6e1da1ca698f",
            # fused (65681 * 2 + 65802 KiB) + fallback (710 * 2 + 162 KiB) per 2^24 elements
            "bytes_per_elem": 12.130}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp")
@@ -196,7 +201,7 @@ def cpu_baseline(v, x, v32, x32, gpu, budget_s):
 def main():
     args = parse()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1 (the elementwise path has no "
+        print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the elementwise path has no "
                                    "cross-GPU step: shard the batch, one process per GPU)"}))
         sys.exit(2)
     import torch

@@ -6,7 +6,7 @@
 // by the method's own range finder (find_bracket at the FP32 margin).  Every
 // predicted bracket is checked after the bins; elements that fail are
 // compacted into a worklist and recomputed by the Newton path, which therefore
-// remains both the fallback and the judge of the predictor.
+// remains both the fallback and the reference for the predictor's error.
 //
 //   features  z = ((log max(|v|, 1e-3) - m_v) / s_v, (log x - m_x) / s_x)
 //   network   h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3
