@@ -379,6 +379,12 @@ def main():
         "paths": paths,
         "learned_range": mlp_info,
         "roofline": roofline,
+        # the paper's own figure, for context only (another stack, another
+        # machine, and a different workload: no ratio is formed with it)
+        "paper_context": {"value": 2e6, "unit": "evals/s", "dtype": "f64",
+                          "hardware": "TensorFlow 2.6, Intel Xeon W-2123 / NVIDIA TITAN RTX (timing device unstated)",
+                          "note": "about 5 ms per call, flat from 10 to 1e4 elements (Section 3.4); 2e6 evals/s "
+                                  "would follow at 1e4 elements"},
     }
     if not args.no_cpu:
         gpu = {
