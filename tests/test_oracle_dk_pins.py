@@ -19,7 +19,8 @@ Independent of the oracle's own formulas:
   and its derivative in v;
 * signs, evenness in v, and the exact zero of odd v-derivatives at v = 0;
 * agreement with the companion-integral first and second derivatives of log K
-  (oracle_logk_hess_batch), which integrate over f's interval instead.
+  (oracle_logk_hess_batch), which integrate over f's interval instead;
+* mpmath's besselk differentiated numerically in v and x at 30 digits.
 """
 
 from math import comb
@@ -156,3 +157,19 @@ def test_matches_companion_integrals():
     check(2, 0, H[:, 3] + H[:, 1] ** 2, 1e-14)
     check(0, 2, H[:, 4] + H[:, 2] ** 2, 1e-14)
     check(1, 1, H[:, 5] + H[:, 1] * H[:, 2], 1e-14)
+
+
+def test_mpmath_derivatives():
+    # a library routine at 30 digits: mpmath's besselk differentiated
+    # numerically in v and x (mp.diff), at stratified points and orders <= 3
+    import mpmath as mp
+    mp.mp.dps = 30
+    pts = [(0.3, 0.05), (1.3, 0.7), (4.5, 2.0), (12.0, 30.0), (25.0, 3.0), (-2.2, 9.0)]
+    for a, b in [(1, 0), (0, 1), (2, 0), (1, 1), (0, 3), (3, 1), (2, 2)]:
+        v = np.array([p[0] for p in pts])
+        x = np.array([p[1] for p in pts])
+        lg, s = oracle.logdk(v, x, a, b)
+        for i, (vi, xi) in enumerate(pts):
+            ref = mp.diff(lambda vv, xx: mp.besselk(vv, xx), (mp.mpf(vi), mp.mpf(xi)), (a, b))
+            got = s[i] * mp.exp(lg[i])
+            assert abs(got - ref) <= 1e-13 * abs(ref), (a, b, vi, xi, float(got), float(ref))
