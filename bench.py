@@ -77,7 +77,7 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the two
 # kernels are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "2708df36f47a3d368fe27a9d8df2761540fad0b906052c43b03e6e1da1ca698f",
+TRAFFIC = {"sources_sha256": "81067e9eca67d513399e0eaf3c5813a750b13f693c16c5b42cd2e4551d93bc1d",
            # fused (65681 * 2 + 65802 KiB) + fallback (710 * 2 + 162 KiB) per 2^24 elements
            "bytes_per_elem": 12.130}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp")
@@ -317,9 +317,9 @@ def main():
         traffic = TRAFFIC["bytes_per_elem"] * args.n
     # batch-size sweep in the paper's shape (Section 3.4: v = 10^{2r} - 1,
     # x = 10^{3r' - 1}): microseconds per call, kernels and launch included;
-    # f64_graph_us replays 50 captured calls per launch (device-side cost)
+    # the *_graph_us entries replay 50 captured calls per launch (device-side cost)
     sweep = {"n": [], "f64_us": [], "f64_one_lane_us": [], "f64_graph_us": [], "f64_one_lane_graph_us": [],
-             "f32_mlp_us": []}
+             "f32_mlp_us": [], "f32_mlp_graph_us": [], "f32_mlp_table_graph_us": []}
     for n_s in () if args.no_sweep else (10, 100, 1000, 10000, 100000, 1000000):
         vs_, xs_ = workloads.paper_sweep(n_s)
         v64s, x64s = torch.tensor(vs_, device=dev), torch.tensor(xs_, device=dev)
@@ -334,6 +334,10 @@ def main():
         bk.set_split_threshold(prev)
         sweep["f32_mlp_us"].append(1e3 * time_path(lambda: bk.logk(v32s, x32s, nbins=nb, range="mlp", mlp=mlp),
                                                    reps, 5))
+        sweep["f32_mlp_graph_us"].append(graph_us_per_call(
+            lambda: bk.logk(v32s, x32s, nbins=nb, range="mlp", mlp=mlp)))
+        sweep["f32_mlp_table_graph_us"].append(graph_us_per_call(
+            lambda: bk.logk(v32s, x32s, nbins=nb, range="mlp_table", mlp=mlp)))
 
     # the FP32 learned-range path against the plain FP64 method on the same batch
     speedup = {"fwd": paths["f32_mlp_fwd"]["evals_per_s"] / paths["f64_fwd"]["evals_per_s"],

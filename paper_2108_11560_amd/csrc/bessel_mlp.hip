@@ -21,6 +21,8 @@
 // values -- then m_v, s_v, m_x, s_x, margin_t1, margin_t0, 0, 0.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstdint>
 #include <cstring>
@@ -991,8 +993,9 @@ static int run_mlp(int64_t n, const float* v, const float* x, const float* go, f
     launch_fused<GRAD, false>(grid, st, m, n, nbins, v, x, go, lk, dv, dx, t0, t1, tp, gp, fb);
   rc = check_launch("k_logk_mlp");
   if (rc) return rc;
-  // persistent fallback grid: 4 blocks per CU
-  const dim3 fgrid(1024);
+  // persistent fallback grid: 4 blocks per CU, fewer for small batches (the
+  // worklist never holds more than n elements)
+  const dim3 fgrid((unsigned)std::min<int64_t>(1024, (n + kBlock - 1) / kBlock));
   switch (nbins) {
     case 64:
       k_logk_fallback<GRAD, 64><<<fgrid, kBlock, 0, st>>>(nbins, m->work, v, x, go, lk, dv, dx, t0, t1, tp, gp);
