@@ -451,3 +451,24 @@ def test_table_gain(mods, trained):
     # the gain over the method without the network (measured 1.16x here, 1.33x
     # at 2^24): the tabulated network's bracket beats the Newton bracket
     assert rate["table_fwd"] >= 1.05 * rate["newton32_fwd"]
+
+
+@pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
+def test_learned_range_outside_training_distribution(mods, trained, mode):
+    # the predictor was trained on v <= 50, x in [1e-3, 1e3]; across the
+    # validated domain (v up to 1e3, x in [1e-6, 1e5]) many predictions miss,
+    # the check sends them to the Newton path, and every result holds the bar
+    bk, M = mods
+    mlp, _ = trained
+    v, x = workloads.domain_pairs(1 << 14, seed=410)
+    vt, xt = dev32(v), dev32(x)
+    lk = bk.logk(vt, xt, range=mode, mlp=mlp)
+    rate = mlp.fallback_count() / v.size
+    ref = bk.logk(vt.double(), xt.double())
+    err = float(((lk.double() - ref).abs() / ref.abs().clamp_min(1.0)).max())
+    print(mode, "fallback", rate, "max err vs FP64", err)
+    assert err <= 1e-5
+    _, dv, dx = bk.logk_dv_dx(vt, xt, range=mode, mlp=mlp)
+    _, rdv, rdx = bk.logk_dv_dx(vt.double(), xt.double())
+    assert float(((dv.double() - rdv).abs() / rdv.abs().clamp_min(1.0)).max()) <= 1e-5
+    assert float(((dx.double() - rdx).abs() / rdx.abs().clamp_min(1.0)).max()) <= 1e-5
