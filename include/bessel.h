@@ -23,6 +23,10 @@
  *     BESSEL_F32 (float) or BESSEL_F64 (double).  The truncation margin log eps
  *     follows the dtype: eps = 2^-23 (F32) or 2^-52 (F64).
  *   - Output arrays must not overlap input arrays (BESSEL_ERR_ALIAS).
+ *   - Sizes: elements are indexed with 64 bits; one call takes up to
+ *     256 (2^31 - 1) elements (the launch grid), the learned range modes up to
+ *     2^31 - 2 (their worklist holds 32-bit indices).  Larger n returns
+ *     BESSEL_ERR_ARG before any work is queued.
  *   - Return value: BESSEL_OK (0), or a negative status; the message of the
  *     last failure on the calling thread is bessel_last_error().  n == 0 is a
  *     no-op that returns BESSEL_OK.
@@ -60,7 +64,7 @@ extern "C" {
 
 /* status codes */
 #define BESSEL_OK 0
-#define BESSEL_ERR_ARG (-1)        /* NULL required pointer, n < 0 */
+#define BESSEL_ERR_ARG (-1)        /* NULL required pointer, n < 0 or above the size limit */
 #define BESSEL_ERR_DTYPE (-2)      /* dtype not BESSEL_F32 / BESSEL_F64 */
 #define BESSEL_ERR_NBINS (-3)      /* nbins outside [BESSEL_MIN_BINS, BESSEL_MAX_BINS] */
 #define BESSEL_ERR_RANGE_MODE (-4) /* unknown range_mode, or a learned range_mode with mlp == NULL */

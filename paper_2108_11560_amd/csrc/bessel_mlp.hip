@@ -640,9 +640,10 @@ __global__ __launch_bounds__(kBlock) void k_logk_fallback(int nbins, const int* 
                                                           float* __restrict__ dv, float* __restrict__ dx,
                                                           float* __restrict__ t0o, float* __restrict__ t1o,
                                                           float* __restrict__ tpo, float* __restrict__ gpo) {
-  const int count = work[0];
+  const int64_t count = work[0];
   const int nb = NB > 0 ? NB : nbins;
-  for (int k = blockIdx.x * kBlock + threadIdx.x; k < count; k += gridDim.x * kBlock) {
+  // 64-bit: with every element on the list, k + stride can pass 2^31
+  for (int64_t k = (int64_t)blockIdx.x * kBlock + threadIdx.x; k < count; k += (int64_t)gridDim.x * kBlock) {
     const int64_t i = work[1 + k];
     const double vs = (double)vin[i];
     const double x = (double)xin[i];
