@@ -47,7 +47,7 @@ __device__ __forceinline__ float hsqrt(float a) { return __builtin_amdgcn_sqrtf(
 // into its double rounding and the residual (Cody-Waite), each applied with a
 // fused multiply-add; e^r by a degree-10 polynomial with minimax relative error
 // 3.0e-16 on |r| <= ln2/2 (coefficients from gen_exp_poly.py); 2^k applied by
-// adding k to the exponent field.
+// ldexp.
 // ---------------------------------------------------------------------------
 constexpr double kLn2D = 6.93147180559945286227e-01;   // ln 2 rounded to double
 constexpr double kLn2Lo = 2.31904681384629955842e-17;  // ln 2 - kLn2D
@@ -79,10 +79,9 @@ __device__ __forceinline__ ExpParts exp_parts(double a) {
   return e;
 }
 
-// x * 2^k for x in [0.5, 2) and 2^k normal: add k to the exponent field.
-__device__ __forceinline__ double scale2k(double x, int k) {
-  return __hiloint2double((int)((unsigned)__double2hiint(x) + ((unsigned)k << 20)), __double2loint(x));
-}
+// x * 2^k (v_ldexp_f64: one full-rate operation, exact while the result is
+// normal, which the callers' ranges keep it).
+__device__ __forceinline__ double scale2k(double x, int k) { return __builtin_amdgcn_ldexp(x, k); }
 
 __device__ __forceinline__ double exp_f64(double a) {
   const ExpParts e = exp_parts(a);

@@ -34,12 +34,13 @@ enum Op {
   RCP_F64,
   FMA64x4_EXP32,  // 4 FP64 FMAs and one FP32 exp per step, independent chains
   SIGMOID,        // 1 / (1 + 2^a): exp, add, rcp
+  LDEXP_F64,      // x 2^k (k = 0 at run time, so the chain keeps its value)
   kNumOps
 };
 
 template <int OP>
 __global__ __launch_bounds__(kThreads) void k_rate(float* __restrict__ of, double* __restrict__ od, float pf,
-                                                  double pd) {
+                                                  double pd, int pk) {
   const int gid = blockIdx.x * kThreads + threadIdx.x;
   float af[kChains];
   double ad[kChains];
@@ -68,6 +69,7 @@ __global__ __launch_bounds__(kThreads) void k_rate(float* __restrict__ of, doubl
         af[i] = __builtin_amdgcn_exp2f(-af[i]);
       }
       if (OP == SIGMOID) af[i] = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(af[i]));
+      if (OP == LDEXP_F64) ad[i] = __builtin_amdgcn_ldexp(ad[i], pk);
     }
   }
   float sf = 0.0f;
@@ -157,7 +159,7 @@ void report(const char* name, double ops, float ms, const char* unit_note) {
 
 template <int OP>
 int run_rate(const char* name, int ops_per_step, float* of, double* od, const char* note) {
-  const float ms = best_ms([&] { k_rate<OP><<<kBlocks, kThreads>>>(of, od, 0.999999f, 0.999999); });
+  const float ms = best_ms([&] { k_rate<OP><<<kBlocks, kThreads>>>(of, od, 0.999999f, 0.999999, 0); });
   if (ms < 0.0f) return 1;
   report(name, (double)kBlocks * kThreads * kIter * kChains * ops_per_step, ms, note);
   return 0;
@@ -203,6 +205,7 @@ int main() {
   rc |= run_rate<FMA64x4_EXP32>("4 v_fma_f64 + 1 v_exp_f32", 5, of, od,
                                 "5 ops per step: slots > 1 means the exp does not overlap the FMAs");
   rc |= run_rate<SIGMOID>("1/(1+2^a): exp + add + rcp", 1, of, od, "slots per activation");
+  rc |= run_rate<LDEXP_F64>("v_ldexp_f64", 1, of, od, "");
   rc |= run_mfma<false>("v_mfma_f32_16x16x32_bf16", of);
   rc |= run_mfma<true>("v_mfma_f32_16x16x32_bf16 + 4 v_exp_f32 per MFMA", of);
   (void)hipFree(of);
