@@ -114,7 +114,7 @@ __device__ __forceinline__ GabAt gab_at(double v, double x, int a, int b, double
 // since g_ab' <= (a+1)/t + b + v - x sinh t, negative beyond t* (sinh t > t) and
 // beyond max(1, t**) (sinh t > (e^t - 1)/2, (a+1)/t <= a+1).  Bisection in
 // log t over 40 octaves below T, then Newton steps kept inside the bracket.
-__device__ double gab_peak(double v, double x, int a, int b) {
+__device__ __forceinline__ double gab_peak(double v, double x, int a, int b) {
   if (a == 0 && (double)b + v * v <= x) return 0.0;
   const double c = (double)b + v;
   const double ts = (c + sqrt(fma(c, c, 4.0 * x * (double)(a + 1)))) / (2.0 * x);
@@ -150,7 +150,7 @@ struct DkBracket {
 // is negative, then rounds of one bisection and one Newton step from the
 // outer end, keeping F >= 0 inside and F < 0 outside.  The outer end is
 // returned, so the bracket is a superset.
-__device__ DkBracket gab_bracket(double v, double x, int a, int b, double L) {
+__device__ __forceinline__ DkBracket gab_bracket(double v, double x, int a, int b, double L) {
   DkBracket br;
   const double tp = gab_peak(v, x, a, b);
   double G, curv;
@@ -253,7 +253,7 @@ __device__ DkBracket gab_bracket(double v, double x, int a, int b, double L) {
 // where rho follows the linear recurrence of u and r (scaled by the constant
 // 1/(u or r)(t_p)) and e^{t_m}, e^{-t_m} run by products re-anchored every
 // kChunk nodes, as in the log K bins.
-__device__ double gab_bins(int nb, double v, double x, int a, int b, const DkBracket& br) {
+__device__ __forceinline__ double gab_bins(int nb, double v, double x, int a, int b, const DkBracket& br) {
   const double t0 = br.t0, t1 = br.t1, tp = br.tp;
   const double h = (t1 - t0) / (double)nb;
   const bool odd = a & 1;
