@@ -318,24 +318,12 @@ __device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G,
 // output dtype.  The search margin adds one nat plus a term proportional to
 // the magnitudes that FP32 rounds, so the FP32 search cannot land inside the
 // exact log-eps set.
-// UNIFORM: the caller's wavefronts tend to agree on v^2 > x and on whether t0
-// is needed (one parameter set per wavefront), so the peak and lower-end
-// searches sit behind branches that whole wavefronts skip.  Otherwise (mixed
-// elements, where a wavefront runs both sides of each branch anyway) they run
-// unconditionally and are selected afterwards, which lets them schedule as
-// one block.
-template <bool UNIFORM = false>
 __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_eps_margin) {
   Bracket b;
   const float vf = (float)v, xf = (float)x;
   const float lx = hlog2(xf);
   float tp = 0.0f;
-  if constexpr (UNIFORM) {
-    if (v * v > x) tp = peak_f32(vf, xf, lx);
-  } else {
-    const float tpk = peak_f32(vf, xf, lx);
-    tp = (v * v > x) ? tpk : 0.0f;
-  }
+  if (v * v > x) tp = peak_f32(vf, xf, lx);
   const double G = g_f64(v, x, (double)tp);
   const float Gf = (float)G;
   const float xcp = hexp2(fmaf(kLog2eF, tp, lx)) + hexp2(fmaf(-kLog2eF, tp, lx));  // 2 x cosh t_p
@@ -344,12 +332,7 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
   b.tp = tp;
   b.t1 = upper_f32(vf, xf, lx, tp, Gf, L);
   const bool need_t0 = (-x - G + (double)L) <= 0.0;
-  if constexpr (UNIFORM) {
-    b.t0 = need_t0 ? lower_f32(vf, lx, tp, Gf, L) : 0.0f;
-  } else {
-    const float t0k = lower_f32(vf, lx, tp, Gf, L);
-    b.t0 = need_t0 ? t0k : 0.0f;
-  }
+  b.t0 = need_t0 ? lower_f32(vf, lx, tp, Gf, L) : 0.0f;
   return b;
 }
 

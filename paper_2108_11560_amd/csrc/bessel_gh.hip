@@ -51,7 +51,7 @@ __global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nc
     double lk, dv, dx;
     if (!domain_special(vs, x, lk, dv, dx)) {
       const double v = fabs(vs);
-      const Bracket b = find_bracket<true>(v, x, kMarginGh);  // one set per wavefront
+      const Bracket b = find_bracket(v, x, kMarginGh);
       const BinSums s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
       const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
       const double rS0 = rcp_of<false>(s.S0);
