@@ -22,6 +22,8 @@ constexpr int kIter = 2048;
 constexpr int kThreads = 256;
 constexpr int kBlocks = 8192;
 
+typedef _Float16 h16x2 __attribute__((ext_vector_type(2)));
+
 enum Op {
   FMA_F32,
   FMA_F64,
@@ -35,6 +37,9 @@ enum Op {
   FMA64x4_EXP32,  // 4 FP64 FMAs and one FP32 exp per step, independent chains
   SIGMOID,        // 1 / (1 + 2^a): exp, add, rcp
   LDEXP_F64,      // x 2^k (k = 0 at run time, so the chain keeps its value)
+  EXP_F16,        // v_exp_f16
+  RCP_F16,        // v_rcp_f16
+  SIGMOID_F16X2,  // two activations in half precision: pack, exp, add, rcp
   kNumOps
 };
 
@@ -44,10 +49,14 @@ __global__ __launch_bounds__(kThreads) void k_rate(float* __restrict__ of, doubl
   const int gid = blockIdx.x * kThreads + threadIdx.x;
   float af[kChains];
   double ad[kChains];
+  _Float16 ah[kChains];
+  float ag[kChains];
 #pragma unroll
   for (int i = 0; i < kChains; ++i) {
     af[i] = 0.5f + 0.01f * (float)(i + (gid & 7));
     ad[i] = 0.5 + 0.01 * (double)(i + (gid & 7));
+    ah[i] = (_Float16)af[i];
+    ag[i] = -af[i];
   }
   for (int it = 0; it < kIter; ++it) {
 #pragma unroll
@@ -70,13 +79,22 @@ __global__ __launch_bounds__(kThreads) void k_rate(float* __restrict__ of, doubl
       }
       if (OP == SIGMOID) af[i] = __builtin_amdgcn_rcpf(1.0f + __builtin_amdgcn_exp2f(af[i]));
       if (OP == LDEXP_F64) ad[i] = __builtin_amdgcn_ldexp(ad[i], pk);
+      if (OP == EXP_F16) ah[i] = __builtin_elementwise_exp2(-ah[i]);
+      if (OP == RCP_F16) ah[i] = __builtin_amdgcn_rcph(ah[i]);
+      if (OP == SIGMOID_F16X2) {
+        const h16x2 p = __builtin_bit_cast(h16x2, __builtin_amdgcn_cvt_pkrtz(af[i], ag[i]));
+        h16x2 e = __builtin_elementwise_exp2(p);
+        e = e + (h16x2){(_Float16)1.0f, (_Float16)1.0f};
+        af[i] = (float)__builtin_amdgcn_rcph(e[0]);
+        ag[i] = (float)__builtin_amdgcn_rcph(e[1]);
+      }
     }
   }
   float sf = 0.0f;
   double sd = 0.0;
 #pragma unroll
   for (int i = 0; i < kChains; ++i) {
-    sf += af[i];
+    sf += af[i] + ag[i] + (float)ah[i];
     sd += ad[i];
   }
   of[gid] = sf;
@@ -206,6 +224,10 @@ int main() {
                                 "5 ops per step: slots > 1 means the exp does not overlap the FMAs");
   rc |= run_rate<SIGMOID>("1/(1+2^a): exp + add + rcp", 1, of, od, "slots per activation");
   rc |= run_rate<LDEXP_F64>("v_ldexp_f64", 1, of, od, "");
+  rc |= run_rate<EXP_F16>("v_exp_f16", 1, of, od, "");
+  rc |= run_rate<RCP_F16>("v_rcp_f16", 1, of, od, "");
+  rc |= run_rate<SIGMOID_F16X2>("2 x 1/(1+2^a) in half precision (with conversions)", 2, of, od,
+                                "slots per activation");
   rc |= run_mfma<false>("v_mfma_f32_16x16x32_bf16", of);
   rc |= run_mfma<true>("v_mfma_f32_16x16x32_bf16 + 4 v_exp_f32 per MFMA", of);
   (void)hipFree(of);
