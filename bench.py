@@ -400,6 +400,11 @@ def main():
                                      gpu, args.cpu_seconds)
         line["cpu_baseline"] = base
         line["max_err_vs_oracle_on_sample"] = errs
+        # the paper's accuracy measure (Section 3.1), log10(|Delta| / eps + 1)
+        # with eps of the path's dtype and Delta the mixed error on log K
+        line["paper_accuracy_measure_on_sample"] = {
+            k: float(np.log10(e / float(np.finfo(np.float64 if k == "f64" else np.float32).eps) + 1.0))
+            for k, e in errs.items()}
     else:
         line["cpu_baseline"] = None
     print(json.dumps(line), flush=True)
