@@ -310,6 +310,8 @@ template <typename T, int NB>
 __global__ __launch_bounds__(kBlock) void k_logdk(int64_t n, int nbins, int a, int b, const T* __restrict__ vin,
                                                   const T* __restrict__ xin, T* __restrict__ out,
                                                   T* __restrict__ sgn) {
+  exp2_table_init();  // the bins run in FP64 for both output types
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int nb = NB > 0 ? NB : nbins;

@@ -88,26 +88,35 @@ __device__ __forceinline__ double exp_f64(double a) {
   return scale2k(1.0 + e.em1, e.k);
 }
 
-// e^a for the nodes of the FP64 bins: the same reduction, e^r by a degree-9
-// minimax polynomial (relative error 1.4e-14 on |r| <= ln2/2, gen_exp_poly.py
-// 9) evaluated to e^r directly.  A node's relative error then stays far below
-// the 1e-12 the FP64 path is held to, for two fewer operations per node.
+// e^a for the nodes of the FP64 bins, from a table: with K the nearest integer
+// to 256 a log2(e), a = K ln2/256 + r and |r| <= ln2/512, so
+//   e^a = 2^{floor(K/256)} 2^{(K mod 256)/256} e^r,
+// the middle factor read from a 256-entry table in LDS (exp2_table, built by
+// every block that uses it) and e^r by a degree-3 minimax polynomial (relative
+// error 1.8e-14 on |r| <= ln2/512; gen_exp_poly.py 3 512).  One multiply and
+// one ldexp apply the table entry and 2^k; the per-node cost is 12 VALU slots
+// against 15 for a degree-9 polynomial on |r| <= ln2/2, at the same accuracy.
+__shared__ double s_exp2_table[256];
+
+// Every thread of a block calls it before any thread of the block reaches
+// exp_node_f64, then the block synchronises.  Blocks have kBlock = 256 threads,
+// one entry each.
+__device__ __forceinline__ void exp2_table_init() {
+  const int j = threadIdx.x & 255;
+  s_exp2_table[j] = exp_f64((double)j * (kLn2D / 256.0));
+}
+
 __device__ __forceinline__ double exp_node_f64(double a) {
   a = fmax(a, -708.0);
-  const double kd = fma(a, kLog2e, kRoundMagic);
+  const double kd = fma(a, 256.0 * kLog2e, kRoundMagic);
   const double kf = kd - kRoundMagic;
-  const double r = fma(-kf, kLn2Lo, fma(-kf, kLn2D, a));
-  double p = 2.748218700193312e-06;
-  p = fma(p, r, 2.4884010015388764e-05);
-  p = fma(p, r, 0.0001984159639703441);
-  p = fma(p, r, 0.0013888802828821594);
-  p = fma(p, r, 0.008333333002822645);
-  p = fma(p, r, 0.041666667032463356);
-  p = fma(p, r, 0.16666666667826954);
-  p = fma(p, r, 0.4999999999945797);
-  p = fma(p, r, 0.9999999999998928);
-  p = fma(p, r, 1.0000000000000127);  // in [0.7, 1.42]
-  return scale2k(p, __double2loint(kd));
+  const double r = fma(-kf, kLn2Lo / 256.0, fma(-kf, kLn2D / 256.0, a));
+  double p = 0.1666666514027065;
+  p = fma(p, r, 0.5000000763659442);
+  p = fma(p, r, 1.0000000000000384);
+  p = fma(p, r, 0.9999999999999825);
+  const int K = __double2loint(kd);
+  return scale2k(s_exp2_table[K & 255] * p, K >> 8);  // K >> 8 = floor(K / 256)
 }
 
 // 1 - e^{-z} for z >= 0 with relative accuracy as z -> 0.

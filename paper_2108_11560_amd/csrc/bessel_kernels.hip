@@ -44,6 +44,10 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
                                                  const T* __restrict__ xin, const T* __restrict__ gout,
                                                  T* __restrict__ logk, T* __restrict__ dv,
                                                  T* __restrict__ dx) {
+  if constexpr (sizeof(T) == 8) {
+    exp2_table_init();
+    __syncthreads();
+  }
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int nb = NB > 0 ? NB : nbins;
@@ -87,6 +91,10 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
                                                       const T* __restrict__ xin, T* __restrict__ logk,
                                                       T* __restrict__ dv, T* __restrict__ dx, T* __restrict__ dvv,
                                                       T* __restrict__ dxx, T* __restrict__ dvx) {
+  if constexpr (sizeof(T) == 8) {
+    exp2_table_init();
+    __syncthreads();
+  }
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
   const int nb = NB > 0 ? NB : nbins;
@@ -139,6 +147,10 @@ __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, con
                                                        const T* __restrict__ xin, const T* __restrict__ gout,
                                                        T* __restrict__ logk, T* __restrict__ dv,
                                                        T* __restrict__ dx) {
+  if constexpr (sizeof(T) == 8) {
+    exp2_table_init();
+    __syncthreads();
+  }
   const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kSplit;
   const int k = (int)(threadIdx.x % kSplit);
   const bool in = e < n;

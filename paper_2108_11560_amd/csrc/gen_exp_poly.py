@@ -1,13 +1,14 @@
 """Generate the polynomial coefficients of the device FP64 exponentials.
 
-e^r on |r| <= ln(2)/2 is approximated by a polynomial of the given degree
+e^r on |r| <= ln(2)/(2 d) is approximated by a polynomial of the given degree
 whose relative error is minimax (Remez exchange on the weight 1/e^r, in
 50-digit mpmath), then rounded to double.  Prints the coefficients and the
 error of the rounded polynomial; the values are pasted into bessel_device.hpp:
-degree 10 for exp_f64 (3.0e-16), degree 9 for the per-node exponential of the
-FP64 bins (about 1e-14, far below the 1e-12 the FP64 path is held to).
+degree 10 with d = 1 for exp_f64 (3.0e-16), degree 3 with d = 256 for the
+per-node exponential of the FP64 bins, whose reduction leaves |r| <= ln2/512
+(1.8e-14, far below the 1e-12 the FP64 path is held to).
 
-    python paper_2108_11560_amd/csrc/gen_exp_poly.py [degree]
+    python paper_2108_11560_amd/csrc/gen_exp_poly.py [degree [d]]
 """
 
 import sys
@@ -16,7 +17,8 @@ import mpmath as mp
 
 mp.mp.dps = 50
 DEG = int(sys.argv[1]) if len(sys.argv) > 1 else 10
-A = mp.log(2) / 2
+DIV = int(sys.argv[2]) if len(sys.argv) > 2 else 1
+A = mp.log(2) / (2 * DIV)
 
 
 def remez(deg, a, iters=30):
@@ -75,7 +77,7 @@ def main():
         worst = max(worst, abs(float((p - mp.e ** r) / mp.e ** r)))
     for j, v in enumerate(cd):
         print(f"c{j} = {v!r}")
-    print(f"max relative error of the rounded polynomial on |r| <= ln2/2: {worst:.3e}")
+    print(f"max relative error of the rounded polynomial on |r| <= ln2/{2 * DIV}: {worst:.3e}")
 
 
 if __name__ == "__main__":
