@@ -16,9 +16,6 @@ import sys
 import mpmath as mp
 
 mp.mp.dps = 50
-DEG = int(sys.argv[1]) if len(sys.argv) > 1 else 10
-DIV = int(sys.argv[2]) if len(sys.argv) > 2 else 1
-A = mp.log(2) / (2 * DIV)
 
 
 def remez(deg, a, iters=30):
@@ -65,19 +62,28 @@ def remez(deg, a, iters=30):
     return coeffs
 
 
-def main():
-    c = remez(DEG, A)
-    cd = [float(v) for v in c]
+def coefficients(deg: int, div: int = 1):
+    """The rounded minimax coefficients c0..c_deg on |r| <= ln(2)/(2 div) and
+    the maximum relative error of the rounded polynomial there."""
+    a = mp.log(2) / (2 * div)
+    cd = [float(v) for v in remez(deg, a)]
     worst = 0.0
     for k in range(20001):
-        r = -A + 2 * A * k / 20000
+        r = -a + 2 * a * k / 20000
         p = mp.mpf(0)
         for v in reversed(cd):
             p = p * r + mp.mpf(v)
         worst = max(worst, abs(float((p - mp.e ** r) / mp.e ** r)))
+    return cd, worst
+
+
+def main():
+    deg = int(sys.argv[1]) if len(sys.argv) > 1 else 10
+    div = int(sys.argv[2]) if len(sys.argv) > 2 else 1
+    cd, worst = coefficients(deg, div)
     for j, v in enumerate(cd):
         print(f"c{j} = {v!r}")
-    print(f"max relative error of the rounded polynomial on |r| <= ln2/{2 * DIV}: {worst:.3e}")
+    print(f"max relative error of the rounded polynomial on |r| <= ln2/{2 * div}: {worst:.3e}")
 
 
 if __name__ == "__main__":
