@@ -1,9 +1,9 @@
 """The GPU path past 2^31 elements (through the C ABI, via the binding).
 
 * Every launch indexes elements with 64 bits: FP32 forward and
-  forward+backward on the Newton bracket over 2^31 + 4 099 pairs, checked
-  against the oracle on the first and last 4 096 elements and 4 096 drawn at
-  random, and finite everywhere.
+  forward+backward and FP64 forward on the Newton bracket over 2^31 + 4 099
+  pairs, checked against the oracle on the first and last 4 096 elements and
+  4 096 drawn at random, and finite everywhere.
 * The learned range keeps its failures on a worklist of 32-bit indices, so it
   accepts at most 2^31 - 2 elements: at that size its outputs, including
   fallbacks at indices above 2^30, match the oracle, and one element more is
@@ -84,6 +84,19 @@ def test_newton_past_2p31(bk, big_pairs):
     assert mixed_err(gather(dv, idx), rdv).max() <= TOL32
     assert mixed_err(gather(dx, idx), rdx).max() <= TOL32
     del lk, dv, dx
+    torch.cuda.empty_cache()
+
+
+def test_newton_fp64_past_2p31(bk, big_pairs):
+    # the FP64 kernels (their exponential reads a table in LDS) at the same size
+    v32, x32 = big_pairs
+    v, x = v32.double(), x32.double()
+    idx = sample(N_BIG, 5)
+    ref = oracle.logk(gather(v, idx), gather(x, idx))
+    lk = bk.logk(v, x, nbins=128)
+    assert bool(torch.isfinite(lk).all())
+    assert mixed_err(gather(lk, idx), ref).max() <= 1e-12
+    del v, x, lk
     torch.cuda.empty_cache()
 
 
