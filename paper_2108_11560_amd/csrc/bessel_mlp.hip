@@ -75,27 +75,37 @@ __global__ __launch_bounds__(kBlock) void k_mlp_labels(int64_t n, const float* _
 }
 
 // ---------------------------------------------------------------------------
-// Training: per-sample forward and backward (FP32), per-block partial
-// gradients, then a fixed-order reduction over blocks (deterministic).
-// One wavefront per block; the block's per-sample vectors are staged in LDS.
+// Training: forward and backward of a block of 64 samples (FP32), per-block
+// partial gradients, then a fixed-order reduction over blocks (deterministic).
+// One wavefront per block.  The three 64 x 64 x 64 products of a block -- the
+// second layer forward (W2 H1), its backward (W2^T D2) and the weight gradient
+// (D2 H1^T) -- run on v_mfma_f32_16x16x4f32 (FP32 operands, FP32
+// accumulation); the rest on the VALU.  Matrices pass through LDS
+// sample-major, [sample][unit], one pad column so that fragment reads along
+// either index hit distinct banks.
+//
+// v_mfma_f32_16x16x4f32, lane l:  A (16 x 4) element [l % 16][l / 16],
+// B (4 x 16) element [l / 16][l % 16], D (16 x 16) elements
+// [4 (l / 16) + r][l % 16], r = 0..3.
 // ---------------------------------------------------------------------------
 constexpr int kTB = 64;  // samples per training block (one wavefront)
 
-// Two staging phases keep the block's LDS under 64 KB: first the vectors of
-// the W2 / b2 / W1 / b1 gradients, then those of W3 / b3.
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
 struct TrainLds {
-  float a[kTB][kH + 1];  // +1 pad: column reads by sample hit distinct banks
-  float b[kTB][kH + 1];
+  float h1[kTB][kH + 1];  // layer-1 activations
+  float d2[kTB][kH + 1];  // layer-2 deltas
+  float c[kTB][kH + 1];   // layer-2 activations, then layer-1 deltas
   float z[kTB][2];
+  float tg[kTB][2];       // targets t0/t1, log t1
   float dy[kTB][2];
   float loss[kTB];
+  int valid[kTB];
 };
 
 // sampled: sample s of the step is index splitmix64(seed ^ step-key ^ s) mod n;
 // otherwise sample s is element s.  Partial gradients of block b go to
 // partial[b * (kNW + 1) .. + kNW), the partial loss to partial[b * (kNW + 1) + kNW].
-// Weights are read with block-uniform indices (scalar loads); the per-sample
-// vectors are fully unrolled into registers.
 __global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, int64_t n, int64_t batch,
                                                   int sampled, uint64_t seed, int64_t step,
                                                   const float* __restrict__ v, const float* __restrict__ x,
@@ -103,102 +113,189 @@ __global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, i
                                                   float alpha, float* __restrict__ partial) {
   __shared__ TrainLds S;
   const int t = threadIdx.x;
-  const int64_t s = (int64_t)blockIdx.x * kTB + t;
-  const bool valid = s < batch;
-  int64_t idx = 0;
-  if (valid)
-    idx = sampled ? (int64_t)(splitmix64(seed ^ ((uint64_t)step * 0x100000001b3ULL) ^ (uint64_t)s) % (uint64_t)n) : s;
-  float z0 = 0.0f, z1 = 0.0f, dy0 = 0.0f, dy1 = 0.0f, lossv = 0.0f;
-  float h1[kH], h2[kH], d2[kH];
-#pragma unroll
-  for (int j = 0; j < kH; ++j) h1[j] = 0.0f;
-#pragma unroll
-  for (int i = 0; i < kH; ++i) h2[i] = 0.0f;
-  if (valid) {
-    mlp_features(P, v[idx], x[idx], z0, z1);
-#pragma unroll
-    for (int j = 0; j < kH; ++j) h1[j] = tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])));
-#pragma unroll
-    for (int i = 0; i < kH; ++i) {
-      float a = P[ob2 + i];
-#pragma unroll
-      for (int j = 0; j < kH; ++j) a = fmaf(P[oW2 + i * kH + j], h1[j], a);
-      h2[i] = tanhf(a);
+  const int lr = t & 15, lg = t >> 4;
+  // layer 1 and the targets, one sample per lane
+  {
+    const int64_t s = (int64_t)blockIdx.x * kTB + t;
+    const bool valid = s < batch;
+    float z0 = 0.0f, z1 = 0.0f, y0t = 0.0f, y1t = 0.0f;
+    if (valid) {
+      const int64_t idx =
+          sampled ? (int64_t)(splitmix64(seed ^ ((uint64_t)step * 0x100000001b3ULL) ^ (uint64_t)s) % (uint64_t)n) : s;
+      mlp_features(P, v[idx], x[idx], z0, z1);
+      const float T0 = lt0[idx], T1 = lt1[idx];
+      y0t = T0 / T1;
+      y1t = logf(T1);
     }
-    float y0 = P[ob3], y1 = P[ob3 + 1];
 #pragma unroll
-    for (int i = 0; i < kH; ++i) {
-      y0 = fmaf(P[oW3 + i], h2[i], y0);
-      y1 = fmaf(P[oW3 + kH + i], h2[i], y1);
-    }
-    const float T0 = lt0[idx], T1 = lt1[idx];
-    const float e0 = y0 - T0 / T1;
-    const float e1 = y1 - logf(T1);
-    const float w0 = e0 > 0.0f ? alpha : 1.0f;
-    const float w1 = e1 < 0.0f ? alpha : 1.0f;
-    const float inv_b = 1.0f / (float)batch;
-    lossv = 0.5f * (w0 * e0 * e0 + w1 * e1 * e1) * inv_b;
-    dy0 = w0 * e0 * inv_b;
-    dy1 = w1 * e1 * inv_b;
-  }
-  // backward through the two tanh layers (all zero for invalid samples)
-#pragma unroll
-  for (int i = 0; i < kH; ++i) d2[i] = fmaf(P[oW3 + i], dy0, P[oW3 + kH + i] * dy1) * (1.0f - h2[i] * h2[i]);
-  S.z[t][0] = z0;
-  S.z[t][1] = z1;
-  S.dy[t][0] = dy0;
-  S.dy[t][1] = dy1;
-  S.loss[t] = lossv;
-  // phase 1: d2 and h1 -> W2, b2; d1 and z -> W1, b1
-#pragma unroll
-  for (int i = 0; i < kH; ++i) S.a[t][i] = d2[i];
-#pragma unroll
-  for (int j = 0; j < kH; ++j) S.b[t][j] = h1[j];
-  float d1[kH];
-#pragma unroll
-  for (int j = 0; j < kH; ++j) {
-    float a = 0.0f;
-#pragma unroll
-    for (int i = 0; i < kH; ++i) a = fmaf(P[oW2 + i * kH + j], d2[i], a);
-    d1[j] = a * (1.0f - h1[j] * h1[j]);
+    for (int j = 0; j < kH; ++j)
+      S.h1[t][j] = valid ? tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]))) : 0.0f;
+    S.z[t][0] = z0;
+    S.z[t][1] = z1;
+    S.tg[t][0] = y0t;
+    S.tg[t][1] = y1t;
+    S.valid[t] = valid ? 1 : 0;
   }
   __syncthreads();
+
+  // layer 2: A2 = W2 H1 + b2, tiles [unit tile it][sample tile st]
+  f32x4 acc[4][4];
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) acc[it][st][r] = P[ob2 + 16 * it + 4 * lg + r];
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    float a[4], b[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) a[it] = P[oW2 + (16 * it + lr) * kH + 4 * ks + lg];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) b[st] = S.h1[16 * st + lr][4 * ks + lg];
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc[it][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[it], b[st], acc[it][st], 0, 0, 0);
+  }
+  // h2 = tanh(A2) and the outputs y = W3 h2 + b3: each lane holds 16 units of
+  // each of its 4 samples; the 4 lanes of a sample (l % 16 equal) add up
+  float y0p[4] = {0.0f, 0.0f, 0.0f, 0.0f}, y1p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * lg + r;
+        const float h = tanhf(acc[it][st][r]);
+        acc[it][st][r] = h;
+        y0p[st] = fmaf(P[oW3 + i], h, y0p[st]);
+        y1p[st] = fmaf(P[oW3 + kH + i], h, y1p[st]);
+      }
+  float dy0[4], dy1[4];
+  const float inv_b = 1.0f / (float)batch;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
+    y0p[st] += __shfl_xor(y0p[st], 16);
+    y0p[st] += __shfl_xor(y0p[st], 32);
+    y1p[st] += __shfl_xor(y1p[st], 16);
+    y1p[st] += __shfl_xor(y1p[st], 32);
+    const int q = 16 * st + lr;
+    dy0[st] = 0.0f;
+    dy1[st] = 0.0f;
+    float lossv = 0.0f;
+    if (S.valid[q]) {
+      const float e0 = (y0p[st] + P[ob3]) - S.tg[q][0];
+      const float e1 = (y1p[st] + P[ob3 + 1]) - S.tg[q][1];
+      const float w0 = e0 > 0.0f ? alpha : 1.0f;
+      const float w1 = e1 < 0.0f ? alpha : 1.0f;
+      lossv = 0.5f * (w0 * e0 * e0 + w1 * e1 * e1) * inv_b;
+      dy0[st] = w0 * e0 * inv_b;
+      dy1[st] = w1 * e1 * inv_b;
+    }
+    if (lg == 0) {
+      S.dy[q][0] = dy0[st];
+      S.dy[q][1] = dy1[st];
+      S.loss[q] = lossv;
+    }
+  }
+  // layer-2 deltas (zero for invalid samples, whose dy is zero)
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 16 * it + 4 * lg + r, q = 16 * st + lr;
+        const float h = acc[it][st][r];
+        S.c[q][i] = h;
+        S.d2[q][i] = fmaf(P[oW3 + i], dy0[st], P[oW3 + kH + i] * dy1[st]) * (1.0f - h * h);
+      }
+  __syncthreads();
+
   float* out = partial + (int64_t)blockIdx.x * (kNW + 1);
-  for (int e = oW2 + t; e < oW3; e += kTB) {
-    float acc = 0.0f;
-    if (e < ob2) {  // W2[i][j]
-      const int i = (e - oW2) >> 6, j = (e - oW2) & 63;
-      for (int q = 0; q < kTB; ++q) acc = fmaf(S.a[q][i], S.b[q][j], acc);
-    } else {  // b2[i]
-      const int i = e - ob2;
-      for (int q = 0; q < kTB; ++q) acc += S.a[q][i];
-    }
-    out[e] = acc;
-  }
-  __syncthreads();
-  // phase 2: d1 -> W1, b1 (with z); h2 -> W3, b3 (with dy)
-#pragma unroll
-  for (int j = 0; j < kH; ++j) S.a[t][j] = d1[j];
-#pragma unroll
-  for (int i = 0; i < kH; ++i) S.b[t][i] = h2[i];
-  __syncthreads();
-  for (int e = t; e < kNW; e += kTB) {
-    if (e >= oW2 && e < oW3) continue;
-    float acc = 0.0f;
-    if (e < ob1) {  // W1[j][k]
-      const int j = e >> 1, k = e & 1;
-      for (int q = 0; q < kTB; ++q) acc = fmaf(S.a[q][j], S.z[q][k], acc);
-    } else if (e < oW2) {  // b1[j]
-      const int j = e - ob1;
-      for (int q = 0; q < kTB; ++q) acc += S.a[q][j];
-    } else if (e < ob3) {  // W3[o][i]
+  // W3, b3 (VALU: 130 values over the 64 samples)
+  for (int e = oW3 + t; e < oMeta; e += kTB) {
+    float a = 0.0f;
+    if (e < ob3) {
       const int o = (e - oW3) >> 6, i = (e - oW3) & 63;
-      for (int q = 0; q < kTB; ++q) acc = fmaf(S.dy[q][o], S.b[q][i], acc);
-    } else {  // b3[o]
+      for (int q = 0; q < kTB; ++q) a = fmaf(S.dy[q][o], S.c[q][i], a);
+    } else {
       const int o = e - ob3;
-      for (int q = 0; q < kTB; ++q) acc += S.dy[q][o];
+      for (int q = 0; q < kTB; ++q) a += S.dy[q][o];
     }
-    out[e] = acc;
+    out[e] = a;
+  }
+  // b2 (VALU)
+  for (int i = t; i < kH; i += kTB) {
+    float a = 0.0f;
+    for (int q = 0; q < kTB; ++q) a += S.d2[q][i];
+    out[ob2 + i] = a;
+  }
+  // layer-1 deltas: D1 = (W2^T D2) (1 - h1^2), tiles [unit tile jt][sample tile st]
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+    for (int st = 0; st < 4; ++st) acc[jt][st] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    float a[4], b[4];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) a[jt] = P[oW2 + (4 * ks + lg) * kH + 16 * jt + lr];
+#pragma unroll
+    for (int st = 0; st < 4; ++st) b[st] = S.d2[16 * st + lr][4 * ks + lg];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int st = 0; st < 4; ++st) acc[jt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jt], b[st], acc[jt][st], 0, 0, 0);
+  }
+  __syncthreads();  // the W3 loop's reads of S.c are done
+#pragma unroll
+  for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+    for (int st = 0; st < 4; ++st)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int j = 16 * jt + 4 * lg + r, q = 16 * st + lr;
+        const float h = S.h1[q][j];
+        S.c[q][j] = acc[jt][st][r] * (1.0f - h * h);
+      }
+  // W2 gradient: D2 H1^T, tiles [unit tile it][unit tile jt], k over samples
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) acc[it][jt] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+  for (int ks = 0; ks < 16; ++ks) {
+    float a[4], b[4];
+#pragma unroll
+    for (int it = 0; it < 4; ++it) a[it] = S.d2[4 * ks + lg][16 * it + lr];
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt) b[jt] = S.h1[4 * ks + lg][16 * jt + lr];
+#pragma unroll
+    for (int it = 0; it < 4; ++it)
+#pragma unroll
+      for (int jt = 0; jt < 4; ++jt) acc[it][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[it], b[jt], acc[it][jt], 0, 0, 0);
+  }
+#pragma unroll
+  for (int it = 0; it < 4; ++it)
+#pragma unroll
+    for (int jt = 0; jt < 4; ++jt)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) out[oW2 + (16 * it + 4 * lg + r) * kH + 16 * jt + lr] = acc[it][jt][r];
+  __syncthreads();  // the layer-1 deltas in S.c
+  // W1, b1 (VALU)
+  for (int e = t; e < oW2; e += kTB) {
+    float a = 0.0f;
+    if (e < ob1) {
+      const int j = e >> 1, k = e & 1;
+      for (int q = 0; q < kTB; ++q) a = fmaf(S.c[q][j], S.z[q][k], a);
+    } else {
+      const int j = e - ob1;
+      for (int q = 0; q < kTB; ++q) a += S.c[q][j];
+    }
+    out[e] = a;
   }
   if (t == 0) {
     float l = 0.0f;
@@ -297,7 +394,6 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restr
 }
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
-typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 // Inference operands, rebuilt from the FP32 parameters whenever they change
 // (k_mlp_pack) so that a wavefront loads its fragments with a few 16-byte loads:
