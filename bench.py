@@ -22,9 +22,11 @@ resident in HBM before timing.  Each path is timed over the whole batch at
 The predictor is trained (20000 Adam steps on 2^20 Newton brackets) and its
 margins calibrated before any timing.  Every launch runs on torch's current
 stream, so the torch.cuda events around the timed region bracket exactly the
-kernels.  Prints ONE JSON line (rank 0).
+kernels.  Each path runs W warm-up calls, then untimed back-to-back calls for
+--warm-seconds (the GPU's clock rises only under sustained load), then K timed
+calls.  Prints ONE JSON line (rank 0).
 
-    python bench.py [--gpus 1] [--steps K] [--warmup W] [--nbins 128] [--no-cpu]
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--warm-seconds S] [--nbins 128] [--no-cpu]
 """
 
 from __future__ import annotations
@@ -110,6 +112,8 @@ def parse():
     p.add_argument("--gpus", type=int, default=1)
     p.add_argument("--steps", type=int, default=20)
     p.add_argument("--warmup", type=int, default=3)
+    p.add_argument("--warm-seconds", type=float, default=0.05,
+                   help="after the warm-up calls, keep calling each path untimed for this long (sustained clock)")
     p.add_argument("--nbins", type=int, default=128)
     p.add_argument("--n", type=int, default=1 << 24)
     p.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline leg")
@@ -125,11 +129,22 @@ def parse():
     return p.parse_args()
 
 
-def time_path(fn, steps, warmup):
+# The GPU raises its clock only under sustained load: a path timed right after
+# an idle gap (host work, a synchronisation, another path's set-up) runs up to
+# ~15 % slower for its first ~20 calls.  Each timed region therefore follows the
+# W warm-up calls and then back-to-back untimed calls of the same path for at
+# least --warm-seconds, so that it measures the sustained rate.
+def time_path(fn, steps, warmup, warm_s=None):
     import torch
+    warm_s = WARM_S if warm_s is None else warm_s
     for _ in range(warmup):
         fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        for _ in range(4):
+            fn()
+        torch.cuda.synchronize()
     start, end = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     start.record()
     for _ in range(steps):
@@ -199,8 +214,13 @@ def cpu_baseline(v, x, v32, x32, gpu, budget_s):
     }, errs, done
 
 
+WARM_S = 0.05
+
+
 def main():
+    global WARM_S
     args = parse()
+    WARM_S = args.warm_seconds
     if args.gpus != 1:
         print(json.dumps({"error": "the benchmark runs on one GPU; --gpus must be 1 (the elementwise path has no "
                                    "cross-GPU step: shard the batch, one process per GPU)"}))
