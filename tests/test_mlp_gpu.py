@@ -10,6 +10,8 @@
   method and against FP32 bins on the Newton bracket.
 """
 
+import time
+
 import numpy as np
 import pytest
 import torch
@@ -277,9 +279,15 @@ def test_mlp_rejects_f64(mods, trained):
         bk.logk(v, v, range="mlp", mlp=mlp)
 
 
-def _evals_per_s(fn, n, reps=5):
+def _evals_per_s(fn, n, reps=5, warm_s=0.05):
+    # back-to-back calls for warm_s first: the GPU raises its clock only under
+    # sustained load, and a path timed cold would read up to ~15 % slow
     fn()
     torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < warm_s:
+        fn()
+        torch.cuda.synchronize()
     a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     a.record()
     for _ in range(reps):
@@ -448,8 +456,8 @@ def test_table_gain(mods, trained):
     assert fallback <= 0.02
     assert rate["table_fwd"] >= 1.2 * rate["f64_fwd"]
     assert rate["table_fwd"] > rate["mlp_fwd"]
-    # the gain over the method without the network (measured 1.16x here, 1.33x
-    # at 2^24): the tabulated network's bracket beats the Newton bracket
+    # the gain over the method without the network (measured about 1.15x, at
+    # 2^22 and 2^24): the tabulated network's bracket beats the Newton bracket
     assert rate["table_fwd"] >= 1.05 * rate["newton32_fwd"]
 
 
