@@ -77,18 +77,22 @@ __global__ __launch_bounds__(kBlock) void k_mlp_labels(int64_t n, const float* _
 // ---------------------------------------------------------------------------
 // Training: forward and backward of a block of 64 samples (FP32), per-block
 // partial gradients, then a fixed-order reduction over blocks (deterministic).
-// One wavefront per block.  The three 64 x 64 x 64 products of a block -- the
-// second layer forward (W2 H1), its backward (W2^T D2) and the weight gradient
-// (D2 H1^T) -- run on v_mfma_f32_16x16x4f32 (FP32 operands, FP32
-// accumulation); the rest on the VALU.  Matrices pass through LDS
-// sample-major, [sample][unit], one pad column so that fragment reads along
-// either index hit distinct banks.
+// Four wavefronts per block; wavefront w owns hidden-unit tile w (units
+// 16w..16w+15) of both layers.  Of the three 64 x 64 x 64 products of a block
+// -- the second layer forward (W2 H1), its backward (W2^T D2) and the weight
+// gradient (D2 H1^T) -- each wavefront computes the 16 rows of its tile, on
+// v_mfma_f32_16x16x4f32 (FP32 operands, FP32 accumulation); the rest runs on
+// the VALU.  Matrices pass through LDS sample-major, [sample][unit], one pad
+// column so that fragment reads along either index hit distinct banks.
 //
 // v_mfma_f32_16x16x4f32, lane l:  A (16 x 4) element [l % 16][l / 16],
 // B (4 x 16) element [l / 16][l % 16], D (16 x 16) elements
 // [4 (l / 16) + r][l % 16], r = 0..3.
 // ---------------------------------------------------------------------------
-constexpr int kTB = 64;  // samples per training block (one wavefront)
+constexpr int kTB = 64;          // samples per training block
+constexpr int kTW = kH / 16;     // wavefronts per training block, one per unit tile
+constexpr int kTT = kTB * kTW;   // threads per training block
+static_assert(oMeta - oW3 <= 3 * kTB && kH <= kTB && oW2 <= 3 * kTB, "the VALU sums fit the block's lanes");
 
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
@@ -99,6 +103,7 @@ struct TrainLds {
   float z[kTB][2];
   float tg[kTB][2];       // targets t0/t1, log t1
   float dy[kTB][2];
+  float yp[kTW][kTB][2];  // each tile's share of the outputs
   float loss[kTB];
   int valid[kTB];
 };
@@ -106,117 +111,131 @@ struct TrainLds {
 // sampled: sample s of the step is index splitmix64(seed ^ step-key ^ s) mod n;
 // otherwise sample s is element s.  Partial gradients of block b go to
 // partial[b * (kNW + 1) .. + kNW), the partial loss to partial[b * (kNW + 1) + kNW].
-__global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, int64_t n, int64_t batch,
+__global__ __launch_bounds__(kTT) void k_mlp_grad(const float* __restrict__ P, int64_t n, int64_t batch,
                                                   int sampled, uint64_t seed, int64_t step,
                                                   const float* __restrict__ v, const float* __restrict__ x,
                                                   const float* __restrict__ lt0, const float* __restrict__ lt1,
                                                   float alpha, float* __restrict__ partial) {
   __shared__ TrainLds S;
   const int t = threadIdx.x;
-  const int lr = t & 15, lg = t >> 4;
-  // layer 1 and the targets, one sample per lane
+  const int w = t >> 6, l = t & 63;  // w: the unit tile (wavefront-uniform)
+  const int lr = l & 15, lg = l >> 4;
+  // layer 1, one sample per lane, the tile's 16 units; wavefront 0 also
+  // keeps the features and the targets
   {
-    const int64_t s = (int64_t)blockIdx.x * kTB + t;
+    const int64_t s = (int64_t)blockIdx.x * kTB + l;
     const bool valid = s < batch;
-    float z0 = 0.0f, z1 = 0.0f, y0t = 0.0f, y1t = 0.0f;
+    float z0 = 0.0f, z1 = 0.0f;
+    int64_t idx = 0;
     if (valid) {
-      const int64_t idx =
-          sampled ? (int64_t)(splitmix64(seed ^ ((uint64_t)step * 0x100000001b3ULL) ^ (uint64_t)s) % (uint64_t)n) : s;
+      idx = sampled ? (int64_t)(splitmix64(seed ^ ((uint64_t)step * 0x100000001b3ULL) ^ (uint64_t)s) % (uint64_t)n)
+                    : s;
       mlp_features(P, v[idx], x[idx], z0, z1);
-      const float T0 = lt0[idx], T1 = lt1[idx];
-      y0t = T0 / T1;
-      y1t = logf(T1);
     }
 #pragma unroll
-    for (int j = 0; j < kH; ++j)
-      S.h1[t][j] = valid ? tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]))) : 0.0f;
-    S.z[t][0] = z0;
-    S.z[t][1] = z1;
-    S.tg[t][0] = y0t;
-    S.tg[t][1] = y1t;
-    S.valid[t] = valid ? 1 : 0;
+    for (int jj = 0; jj < 16; ++jj) {
+      const int j = 16 * w + jj;
+      S.h1[l][j] = valid ? tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]))) : 0.0f;
+    }
+    if (w == 0) {
+      float y0t = 0.0f, y1t = 0.0f;
+      if (valid) {
+        const float T0 = lt0[idx], T1 = lt1[idx];
+        y0t = T0 / T1;
+        y1t = logf(T1);
+      }
+      S.z[l][0] = z0;
+      S.z[l][1] = z1;
+      S.tg[l][0] = y0t;
+      S.tg[l][1] = y1t;
+      S.valid[l] = valid ? 1 : 0;
+    }
   }
   __syncthreads();
 
-  // layer 2: A2 = W2 H1 + b2, tiles [unit tile it][sample tile st]
-  f32x4 acc[4][4];
+  // layer 2 of the tile: A2 = W2 H1 + b2, tiles [w][sample tile st]
+  f32x4 acc[4];
 #pragma unroll
-  for (int it = 0; it < 4; ++it)
+  for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) acc[it][st][r] = P[ob2 + 16 * it + 4 * lg + r];
+    for (int r = 0; r < 4; ++r) acc[st][r] = P[ob2 + 16 * w + 4 * lg + r];
 #pragma unroll
   for (int ks = 0; ks < 16; ++ks) {
-    float a[4], b[4];
-#pragma unroll
-    for (int it = 0; it < 4; ++it) a[it] = P[oW2 + (16 * it + lr) * kH + 4 * ks + lg];
+    const float a = P[oW2 + (16 * w + lr) * kH + 4 * ks + lg];
+    float b[4];
 #pragma unroll
     for (int st = 0; st < 4; ++st) b[st] = S.h1[16 * st + lr][4 * ks + lg];
 #pragma unroll
-    for (int it = 0; it < 4; ++it)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) acc[it][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[it], b[st], acc[it][st], 0, 0, 0);
+    for (int st = 0; st < 4; ++st) acc[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[st], acc[st], 0, 0, 0);
   }
-  // h2 = tanh(A2) and the outputs y = W3 h2 + b3: each lane holds 16 units of
-  // each of its 4 samples; the 4 lanes of a sample (l % 16 equal) add up
+  // h2 = tanh(A2) and the tile's share of y = W3 h2 + b3: each lane holds 4
+  // units of each of its 4 samples; the 4 lanes of a sample (l % 16 equal)
+  // add up, then the shares of the tiles meet in LDS
   float y0p[4] = {0.0f, 0.0f, 0.0f, 0.0f}, y1p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
-  for (int it = 0; it < 4; ++it)
+  for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * lg + r;
-        const float h = tanhf(acc[it][st][r]);
-        acc[it][st][r] = h;
-        y0p[st] = fmaf(P[oW3 + i], h, y0p[st]);
-        y1p[st] = fmaf(P[oW3 + kH + i], h, y1p[st]);
-      }
-  float dy0[4], dy1[4];
-  const float inv_b = 1.0f / (float)batch;
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + 4 * lg + r;
+      const float h = tanhf(acc[st][r]);
+      acc[st][r] = h;
+      y0p[st] = fmaf(P[oW3 + i], h, y0p[st]);
+      y1p[st] = fmaf(P[oW3 + kH + i], h, y1p[st]);
+    }
 #pragma unroll
   for (int st = 0; st < 4; ++st) {
     y0p[st] += __shfl_xor(y0p[st], 16);
     y0p[st] += __shfl_xor(y0p[st], 32);
     y1p[st] += __shfl_xor(y1p[st], 16);
     y1p[st] += __shfl_xor(y1p[st], 32);
+    if (lg == 0) {
+      S.yp[w][16 * st + lr][0] = y0p[st];
+      S.yp[w][16 * st + lr][1] = y1p[st];
+    }
+  }
+  __syncthreads();
+  // output errors (every wavefront, the same sums in the same order)
+  float dy0[4], dy1[4];
+  const float inv_b = 1.0f / (float)batch;
+#pragma unroll
+  for (int st = 0; st < 4; ++st) {
     const int q = 16 * st + lr;
     dy0[st] = 0.0f;
     dy1[st] = 0.0f;
     float lossv = 0.0f;
     if (S.valid[q]) {
-      const float e0 = (y0p[st] + P[ob3]) - S.tg[q][0];
-      const float e1 = (y1p[st] + P[ob3 + 1]) - S.tg[q][1];
+      const float y0 = (S.yp[0][q][0] + S.yp[1][q][0]) + (S.yp[2][q][0] + S.yp[3][q][0]);
+      const float y1 = (S.yp[0][q][1] + S.yp[1][q][1]) + (S.yp[2][q][1] + S.yp[3][q][1]);
+      const float e0 = (y0 + P[ob3]) - S.tg[q][0];
+      const float e1 = (y1 + P[ob3 + 1]) - S.tg[q][1];
       const float w0 = e0 > 0.0f ? alpha : 1.0f;
       const float w1 = e1 < 0.0f ? alpha : 1.0f;
       lossv = 0.5f * (w0 * e0 * e0 + w1 * e1 * e1) * inv_b;
       dy0[st] = w0 * e0 * inv_b;
       dy1[st] = w1 * e1 * inv_b;
     }
-    if (lg == 0) {
+    if (w == 0 && lg == 0) {
       S.dy[q][0] = dy0[st];
       S.dy[q][1] = dy1[st];
       S.loss[q] = lossv;
     }
   }
-  // layer-2 deltas (zero for invalid samples, whose dy is zero)
+  // layer-2 deltas of the tile (zero for invalid samples, whose dy is zero)
 #pragma unroll
-  for (int it = 0; it < 4; ++it)
+  for (int st = 0; st < 4; ++st)
 #pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 16 * it + 4 * lg + r, q = 16 * st + lr;
-        const float h = acc[it][st][r];
-        S.c[q][i] = h;
-        S.d2[q][i] = fmaf(P[oW3 + i], dy0[st], P[oW3 + kH + i] * dy1[st]) * (1.0f - h * h);
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int i = 16 * w + 4 * lg + r, q = 16 * st + lr;
+      const float h = acc[st][r];
+      S.c[q][i] = h;
+      S.d2[q][i] = fmaf(P[oW3 + i], dy0[st], P[oW3 + kH + i] * dy1[st]) * (1.0f - h * h);
+    }
   __syncthreads();
 
   float* out = partial + (int64_t)blockIdx.x * (kNW + 1);
-  // W3, b3 (VALU: 130 values over the 64 samples)
-  for (int e = oW3 + t; e < oMeta; e += kTB) {
+  if (t < oMeta - oW3) {
+    // W3, b3 (VALU: 130 values over the 64 samples), wavefronts 0-2
+    const int e = oW3 + t;
     float a = 0.0f;
     if (e < ob3) {
       const int o = (e - oW3) >> 6, i = (e - oW3) & 63;
@@ -226,67 +245,56 @@ __global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, i
       for (int q = 0; q < kTB; ++q) a += S.dy[q][o];
     }
     out[e] = a;
-  }
-  // b2 (VALU)
-  for (int i = t; i < kH; i += kTB) {
+  } else if (t >= 3 * kTB && t < 3 * kTB + kH) {
+    // b2 (VALU), wavefront 3
+    const int i = t - 3 * kTB;
     float a = 0.0f;
     for (int q = 0; q < kTB; ++q) a += S.d2[q][i];
     out[ob2 + i] = a;
   }
-  // layer-1 deltas: D1 = (W2^T D2) (1 - h1^2), tiles [unit tile jt][sample tile st]
+  // layer-1 deltas of the tile: D1 = (W2^T D2) (1 - h1^2), tiles [w][sample tile st]
+  f32x4 acc1[4];
 #pragma unroll
-  for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-    for (int st = 0; st < 4; ++st) acc[jt][st] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  for (int st = 0; st < 4; ++st) acc1[st] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int ks = 0; ks < 16; ++ks) {
-    float a[4], b[4];
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt) a[jt] = P[oW2 + (4 * ks + lg) * kH + 16 * jt + lr];
+    const float a = P[oW2 + (4 * ks + lg) * kH + 16 * w + lr];
+    float b[4];
 #pragma unroll
     for (int st = 0; st < 4; ++st) b[st] = S.d2[16 * st + lr][4 * ks + lg];
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-      for (int st = 0; st < 4; ++st) acc[jt][st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[jt], b[st], acc[jt][st], 0, 0, 0);
+    for (int st = 0; st < 4; ++st) acc1[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[st], acc1[st], 0, 0, 0);
   }
-  __syncthreads();  // the W3 loop's reads of S.c are done
+  // W2 gradient, rows of the tile: D2 H1^T, tiles [w][unit tile jt], k over samples
+  f32x4 accw[4];
 #pragma unroll
-  for (int jt = 0; jt < 4; ++jt)
-#pragma unroll
-    for (int st = 0; st < 4; ++st)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int j = 16 * jt + 4 * lg + r, q = 16 * st + lr;
-        const float h = S.h1[q][j];
-        S.c[q][j] = acc[jt][st][r] * (1.0f - h * h);
-      }
-  // W2 gradient: D2 H1^T, tiles [unit tile it][unit tile jt], k over samples
-#pragma unroll
-  for (int it = 0; it < 4; ++it)
-#pragma unroll
-    for (int jt = 0; jt < 4; ++jt) acc[it][jt] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+  for (int jt = 0; jt < 4; ++jt) accw[jt] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
 #pragma unroll
   for (int ks = 0; ks < 16; ++ks) {
-    float a[4], b[4];
-#pragma unroll
-    for (int it = 0; it < 4; ++it) a[it] = S.d2[4 * ks + lg][16 * it + lr];
+    const float a = S.d2[4 * ks + lg][16 * w + lr];
+    float b[4];
 #pragma unroll
     for (int jt = 0; jt < 4; ++jt) b[jt] = S.h1[4 * ks + lg][16 * jt + lr];
 #pragma unroll
-    for (int it = 0; it < 4; ++it)
-#pragma unroll
-      for (int jt = 0; jt < 4; ++jt) acc[it][jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[it], b[jt], acc[it][jt], 0, 0, 0);
+    for (int jt = 0; jt < 4; ++jt) accw[jt] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[jt], accw[jt], 0, 0, 0);
   }
 #pragma unroll
-  for (int it = 0; it < 4; ++it)
+  for (int jt = 0; jt < 4; ++jt)
 #pragma unroll
-    for (int jt = 0; jt < 4; ++jt)
+    for (int r = 0; r < 4; ++r) out[oW2 + (16 * w + 4 * lg + r) * kH + 16 * jt + lr] = accw[jt][r];
+  __syncthreads();  // every read of S.c (the W3 sums) is done
 #pragma unroll
-      for (int r = 0; r < 4; ++r) out[oW2 + (16 * it + 4 * lg + r) * kH + 16 * jt + lr] = acc[it][jt][r];
+  for (int st = 0; st < 4; ++st)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int j = 16 * w + 4 * lg + r, q = 16 * st + lr;
+      const float h = S.h1[q][j];
+      S.c[q][j] = acc1[st][r] * (1.0f - h * h);
+    }
   __syncthreads();  // the layer-1 deltas in S.c
-  // W1, b1 (VALU)
-  for (int e = t; e < oW2; e += kTB) {
+  if (t < oW2) {
+    // W1, b1 (VALU: 192 values), wavefronts 0-2
+    const int e = t;
     float a = 0.0f;
     if (e < ob1) {
       const int j = e >> 1, k = e & 1;
@@ -296,26 +304,27 @@ __global__ __launch_bounds__(kTB) void k_mlp_grad(const float* __restrict__ P, i
       for (int q = 0; q < kTB; ++q) a += S.c[q][j];
     }
     out[e] = a;
-  }
-  if (t == 0) {
-    float l = 0.0f;
-    for (int q = 0; q < kTB; ++q) l += S.loss[q];
-    out[kNW] = l;
+  } else if (t == 3 * kTB) {
+    float ls = 0.0f;
+    for (int q = 0; q < kTB; ++q) ls += S.loss[q];
+    out[kNW] = ls;
   }
 }
 
 // grad[e] = sum over blocks of partial[b][e] in block order; loss likewise.
 // Sum over blocks of value e of the partials, in block order (deterministic);
-// eight loads in flight per group.
+// 32 loads in flight per group (the sum is latency-bound: a few hundred
+// threads in all).
 __device__ __forceinline__ float reduce_partials(const float* __restrict__ partial, int nblocks, int e) {
+  constexpr int kFly = 32;
   double acc = 0.0;
   int b = 0;
-  for (; b + 8 <= nblocks; b += 8) {
-    float p[8];
+  for (; b + kFly <= nblocks; b += kFly) {
+    float p[kFly];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) p[j] = partial[(int64_t)(b + j) * (kNW + 1) + e];
+    for (int j = 0; j < kFly; ++j) p[j] = partial[(int64_t)(b + j) * (kNW + 1) + e];
 #pragma unroll
-    for (int j = 0; j < 8; ++j) acc += (double)p[j];
+    for (int j = 0; j < kFly; ++j) acc += (double)p[j];
   }
   for (; b < nblocks; ++b) acc += (double)partial[(int64_t)b * (kNW + 1) + e];
   return (float)acc;
@@ -902,7 +911,7 @@ static int launch_partials(bessel_mlp* m, int64_t n, int64_t batch, int sampled,
   nblocks = (batch + kTB - 1) / kTB;
   int rc = ensure(m->partial, m->cap_partial_blocks, nblocks * (kNW + 1), st, "partial gradients");
   if (rc) return rc;
-  k_mlp_grad<<<dim3((unsigned)nblocks), kTB, 0, st>>>(m->params, n, batch, sampled, seed, step, v, x, t0, t1,
+  k_mlp_grad<<<dim3((unsigned)nblocks), kTT, 0, st>>>(m->params, n, batch, sampled, seed, step, v, x, t0, t1,
                                                       alpha, m->partial);
   return check_launch("k_mlp_grad");
 }
