@@ -501,7 +501,9 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   for (int c = 0; c < nchunks; ++c) {
     // the linear part runs by addition inside a chunk (error <= kChunk32 ulp of |L|)
     double L = fma((double)(c * kChunk32), dL, L0);
-    const double ta = fma((double)(c * kChunk32), h, t0);
+    // node time, by addition likewise: an index literal in fma(b, h, t) would
+    // cost a copy per node (the three-operand FMA takes no literal)
+    double t = fma((double)(c * kChunk32), h, t0);
 #pragma unroll
     for (int b = 0; b < kChunk32; ++b) {
       float w = hexp2((float)fma(-xl, C, L));
@@ -510,7 +512,7 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
       const double wd = (double)w;
       S[b & 1] = fma(wd, u, S[b & 1]);
       if (GRAD) {
-        const double t = fma((double)b, h, ta), wr = wd * r, wu = wd * u;
+        const double wr = wd * r, wu = wd * u;
         Sv[b & 1] = fma(wr, t, Sv[b & 1]);
         Sx[b & 1] = fma(wu, C, Sx[b & 1]);
         if (DER >= 2) {
@@ -519,6 +521,7 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
           Svx[b & 1] = fma(wr * t, C, Svx[b & 1]);
         }
         r = fma(r, Q, E2);
+        t += h;
       }
       u = fma(u, Q, E2);
       L += dL;
