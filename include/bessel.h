@@ -303,6 +303,27 @@ int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, cons
                        float* g_alpha, float* g_delta, float* g_mu, int nbins, int range_mode,
                        const bessel_mlp* mlp, void* hip_stream);
 
+/*
+ * bessel_gh_logk_sum_noalloc -- bessel_gh_logk_sum without any allocation, for
+ * callers that cannot allocate device memory during the call (code under HIP
+ * graph capture, serving loops, harnesses that forbid hipMalloc).  Arguments,
+ * results and errors are those of bessel_gh_logk_sum (the same kernels, so the
+ * same bits), except that the per-block partial sums live in a static device
+ * array of the library instead of a temporary: at most
+ * BESSEL_GH_NOALLOC_MAX_BLOCKS records, i.e. nsets * ceil(nsamp / 256) must not
+ * exceed it (else BESSEL_ERR_ARG before any work is queued; 1024 sets of 65536
+ * samples fit).  Each GPU the library runs on holds that array (10 MiB) until
+ * the process ends; the first call on a GPU looks up its address there.  Every
+ * call on one GPU shares the array: calls that overlap in time on one GPU (on
+ * different streams, or from different host threads) race and must be
+ * serialised by the caller.  Nothing in the array needs clearing between calls.
+ */
+#define BESSEL_GH_NOALLOC_MAX_BLOCKS (1LL << 18)
+int bessel_gh_logk_sum_noalloc(int64_t nsets, const float* lam, const float* alpha, const float* delta,
+                               const float* mu, int64_t nsamp, const float* y, const float* grad_sum, float* sum,
+                               float* g_lam, float* g_alpha, float* g_delta, float* g_mu, int nbins,
+                               int range_mode, const bessel_mlp* mlp, void* hip_stream);
+
 /* Message of the last failed call on the calling thread ("" if none). */
 const char* bessel_last_error(void);
 

@@ -54,6 +54,8 @@ SIGNATURES = {
     "bessel_mlp_fallback_count": (_int, [_vp, _vp]),
     "bessel_gh_logk_sum": (_int, [_i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int, _int,
                                   _vp, _vp]),
+    "bessel_gh_logk_sum_noalloc": (_int, [_i64, _vp, _vp, _vp, _vp, _i64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _int,
+                                          _int, _vp, _vp]),
     "bessel_last_error": (ctypes.c_char_p, []),
     "bessel_version": (ctypes.c_char_p, []),
 }

@@ -14,7 +14,9 @@
 // of each set in chunk order (deterministic).
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cstdint>
+#include <mutex>
 
 #include "bessel.h"
 #include "bessel_device.hpp"
@@ -99,15 +101,55 @@ __global__ __launch_bounds__(kBlock) void k_gh_final(int64_t nsets, int64_t nchu
   if (g_mu) g_mu[i] = (float)(g * acc[4]);
 }
 
-}  // namespace bk
+// Partials of bessel_gh_logk_sum_noalloc: one record of kGhQ doubles per
+// (set, chunk) block, at most kGhScratchBlocks blocks (10 MiB: 1024 sets of
+// 65536 samples).  Each GPU holds its own copy for the life of the process;
+// host code reaches it only through the address hipGetSymbolAddress returns
+// for that GPU (gh_scratch below), never through the array's name.
+constexpr int64_t kGhScratchBlocks = BESSEL_GH_NOALLOC_MAX_BLOCKS;
+static __device__ __align__(256) double scratch[kGhScratchBlocks * kGhQ];
 
-using namespace bk;
+constexpr int kMaxDevices = 64;
+static std::atomic<double*> g_scratch_ptr[kMaxDevices];
+static std::mutex g_scratch_mu;
 
-extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, const float* delta,
-                                  const float* mu, int64_t nsamp, const float* y, const float* grad_sum, float* sum,
-                                  float* g_lam, float* g_alpha, float* g_delta, float* g_mu, int nbins,
-                                  int range_mode, const bessel_mlp* mlp, void* hip_stream) {
-  (void)mlp;
+// The device address of `scratch` on the device that runs work queued on st
+// (the stream's device, or the current device for the null stream), looked up
+// once per device with that device current.
+static int gh_scratch(hipStream_t st, double** out) {
+  int dev = 0;
+  hipError_t e = st ? hipStreamGetDevice(st, &dev) : hipGetDevice(&dev);
+  if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "device of the stream: %s", hipGetErrorString(e));
+  if (dev < 0 || dev >= kMaxDevices) return set_error(BESSEL_ERR_ARG, "device %d beyond %d", dev, kMaxDevices);
+  double* p = g_scratch_ptr[dev].load(std::memory_order_acquire);
+  if (!p) {
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch_ptr[dev].load(std::memory_order_relaxed);
+    if (!p) {
+      int cur = 0;
+      e = hipGetDevice(&cur);
+      if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+      void* addr = nullptr;
+      if (e == hipSuccess) e = hipGetSymbolAddress(&addr, HIP_SYMBOL(scratch));
+      const hipError_t e2 = (cur != dev) ? hipSetDevice(cur) : hipSuccess;
+      if (e == hipSuccess) e = e2;
+      if (e != hipSuccess || !addr)
+        return set_error(BESSEL_ERR_HIP, "address of the static partials: %s", hipGetErrorString(e));
+      p = static_cast<double*>(addr);
+      g_scratch_ptr[dev].store(p, std::memory_order_release);
+    }
+  }
+  *out = p;
+  return BESSEL_OK;
+}
+
+namespace {
+
+// Argument checks shared by both entry points; nblocks receives the number of
+// (set, chunk) blocks, i.e. of partial records the call needs.
+int gh_checks(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
+              int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam, float* g_alpha,
+              float* g_delta, float* g_mu, int nbins, int range_mode, int64_t& nchunks, int64_t& nblocks) {
   if (nsets < 0 || nsamp < 0) return set_error(BESSEL_ERR_ARG, "nsets and nsamp must be >= 0");
   if (range_mode != BESSEL_RANGE_NEWTON)
     return set_error(range_mode == BESSEL_RANGE_MLP || range_mode == BESSEL_RANGE_MLP_TABLE ? BESSEL_ERR_UNSUPPORTED
@@ -115,6 +157,8 @@ extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* 
                      "the per-set sums use the Newton bracket");
   if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
     return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
+  nchunks = nsamp > 0 ? (nsamp + kBlock - 1) / kBlock : 1;
+  nblocks = 0;
   if (nsets == 0) return BESSEL_OK;
   if (!lam || !alpha || !delta || !mu || !sum || (nsamp > 0 && !y))
     return set_error(BESSEL_ERR_ARG, "lam, alpha, delta, mu, sum and y must be non-NULL");
@@ -128,13 +172,18 @@ extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* 
     for (int b = a + 1; b < 5; ++b)
       if (overlaps(outs[a], sb, outs[b], sb)) return set_error(BESSEL_ERR_ALIAS, "two outputs overlap");
   }
-  const int64_t nchunks = nsamp > 0 ? (nsamp + kBlock - 1) / kBlock : 1;
-  const int64_t nblocks = nsets * nchunks;
-  if (nblocks > 0x7fffffffLL) return set_error(BESSEL_ERR_ARG, "nsets x nsamp too large for one launch");
-  hipStream_t st = (hipStream_t)hip_stream;
-  double* partial = nullptr;
-  hipError_t e = hipMallocAsync((void**)&partial, (size_t)nblocks * kGhQ * sizeof(double), st);
-  if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
+  if (nchunks > 0x7fffffffLL / nsets) return set_error(BESSEL_ERR_ARG, "nsets x nsamp too large for one launch");
+  nblocks = nsets * nchunks;
+  return BESSEL_OK;
+}
+
+// The two kernels of a call, with the partial records at `partial`
+// (nblocks * kGhQ doubles, every one written by k_gh_partial before
+// k_gh_final reads it, so nothing needs clearing).
+int gh_launch(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
+              int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam, float* g_alpha,
+              float* g_delta, float* g_mu, int nbins, int64_t nchunks, int64_t nblocks, double* partial,
+              hipStream_t st) {
   const dim3 grid((unsigned)nblocks);
   switch (nbins) {
     case 64: k_gh_partial<64><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
@@ -143,12 +192,54 @@ extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* 
     default: k_gh_partial<0><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
   }
   int rc = check_launch("k_gh_partial");
-  if (rc == BESSEL_OK) {
-    k_gh_final<<<dim3((unsigned)((nsets + kBlock - 1) / kBlock)), kBlock, 0, st>>>(nsets, nchunks, partial, grad_sum,
-                                                                               sum, g_lam, g_alpha, g_delta, g_mu);
-    rc = check_launch("k_gh_final");
-  }
+  if (rc) return rc;
+  k_gh_final<<<dim3((unsigned)((nsets + kBlock - 1) / kBlock)), kBlock, 0, st>>>(nsets, nchunks, partial, grad_sum,
+                                                                             sum, g_lam, g_alpha, g_delta, g_mu);
+  return check_launch("k_gh_final");
+}
+
+}  // namespace
+
+}  // namespace bk
+
+using namespace bk;
+
+extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, const float* delta,
+                                  const float* mu, int64_t nsamp, const float* y, const float* grad_sum, float* sum,
+                                  float* g_lam, float* g_alpha, float* g_delta, float* g_mu, int nbins,
+                                  int range_mode, const bessel_mlp* mlp, void* hip_stream) {
+  (void)mlp;
+  int64_t nchunks = 0, nblocks = 0;
+  int rc = gh_checks(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
+                     range_mode, nchunks, nblocks);
+  if (rc || nsets == 0) return rc;
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* partial = nullptr;
+  hipError_t e = hipMallocAsync((void**)&partial, (size_t)nblocks * kGhQ * sizeof(double), st);
+  if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
+  rc = gh_launch(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins, nchunks,
+                 nblocks, partial, st);
   e = hipFreeAsync(partial, st);
   if (rc == BESSEL_OK && e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
   return rc;
+}
+
+extern "C" int bessel_gh_logk_sum_noalloc(int64_t nsets, const float* lam, const float* alpha, const float* delta,
+                                          const float* mu, int64_t nsamp, const float* y, const float* grad_sum,
+                                          float* sum, float* g_lam, float* g_alpha, float* g_delta, float* g_mu,
+                                          int nbins, int range_mode, const bessel_mlp* mlp, void* hip_stream) {
+  (void)mlp;
+  int64_t nchunks = 0, nblocks = 0;
+  int rc = gh_checks(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
+                     range_mode, nchunks, nblocks);
+  if (rc || nsets == 0) return rc;
+  if (nblocks > kGhScratchBlocks)
+    return set_error(BESSEL_ERR_ARG, "nsets x ceil(nsamp / %d) = %lld exceeds the %lld records of the static partials",
+                     kBlock, (long long)nblocks, (long long)kGhScratchBlocks);
+  hipStream_t st = (hipStream_t)hip_stream;
+  double* partial = nullptr;
+  rc = gh_scratch(st, &partial);
+  if (rc) return rc;
+  return gh_launch(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
+                   nchunks, nblocks, partial, st);
 }

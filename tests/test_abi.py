@@ -122,6 +122,22 @@ def test_gh_argument_errors(lib):
     assert lib.bessel_gh_logk_sum(0, *args, 128, 0, NULL, NULL) == 0
     bad = [FAKE_A, FAKE_A, FAKE_A, FAKE_A, 4, FAKE_B, NULL, FAKE_A, NULL, NULL, NULL, NULL]
     assert lib.bessel_gh_logk_sum(4, *bad, 128, 0, NULL, NULL) == -6
+    # the allocation-free variant runs the same checks first
+    for fn in (lib.bessel_gh_logk_sum, lib.bessel_gh_logk_sum_noalloc):
+        assert fn(4, *args, 128, 2, NULL, NULL) == -7
+        assert fn(4, *args, 1, 0, NULL, NULL) == -3
+        assert fn(4, *bad, 128, 0, NULL, NULL) == -6
+        assert fn(0, *args, 128, 0, NULL, NULL) == 0
+
+
+def test_gh_noalloc_rejects_beyond_its_static_partials(lib):
+    # 1025 sets x 256 chunks of 256 samples: one set more than the static array
+    # holds; the host check returns before any GPU call
+    sets = [ctypes.c_void_p(0x1000000 * (k + 1)) for k in range(4)]
+    y, out = ctypes.c_void_p(0x10000000), ctypes.c_void_p(0x20000000)
+    rc = lib.bessel_gh_logk_sum_noalloc(1025, *sets, 65536, y, NULL, out, NULL, NULL, NULL, NULL, 128, 0, NULL, NULL)
+    assert rc == -1
+    assert "static partials" in err(lib)
 
 
 def test_mlp_argument_errors(lib):
