@@ -366,8 +366,14 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
 // ---------------------------------------------------------------------------
 struct BinSums {
   double S0, Sv, Sx;
-  // second-derivative sums (DER == 2): t^2 f, cosh^2 t f, t cosh t sinh(vt) e^{-x cosh t}
+  // second-derivative sums (DER == 2).  FP32 bins: t^2 f, cosh^2 t f and
+  // t cosh t sinh(vt) e^{-x cosh t}.  FP64 bins: moments about centres a, b
+  // near the peak (bins_f64), so that the variances they form do not cancel:
+  // Svv = sum f (t - a)^2, Sxx = sum f (C - b)^2, Svx = sum d/dv f (C - b),
+  // and Sv1 = sum f (t - a), Sx1 = sum f (C - b), Sq = sum 2 e^{A} e^{-2vt} t,
+  // the last being sum (t f - d/dv f) with C = cosh t, f = e^{A} (1 + e^{-2vt}).
   double Svv, Sxx, Svx;
+  double Sv1, Sx1, Sq;
   // Filled only by the checked FP32 variant (learned brackets): the sums over
   // even and over odd nodes (each a trapezoid / midpoint rule of step 2h; their
   // difference measures the quadrature error), and the unweighted terms at the
@@ -379,14 +385,34 @@ struct BinSums {
 constexpr int kChunk = 16;    // nodes per unrolled chunk (FP64 bins)
 constexpr int kChunk32 = 32;  // nodes per unrolled chunk (FP32 bins)
 
+// Second-order moments of one FP64 node (DER == 2), about the centres a (t)
+// and b (cosh t): with wu = e^{A} u (f) and wr = e^{A} r (d/dv f / t),
+//   M0 += wu (t - a)^2,  M1 += wu (C - b)^2,  M2 += wr t (C - b),
+//   M3 += wu (t - a),    M4 += wu (C - b),    M5 += (wu - wr) t.
+// Six sums, 12 operations a node against 6 for the raw moments t^2 f,
+// C^2 f, t C d/dv f; each sum is its own chain, so no even/odd split.
+__device__ __forceinline__ void moments(double wu, double wr, double t, double C, double a, double b, double* M) {
+  const double Y = C - b, d = t - a;
+  const double wuY = wu * Y, wud = wu * d;
+  M[1] = fma(wuY, Y, M[1]);
+  M[4] += wuY;
+  M[2] = fma(wr * t, Y, M[2]);
+  M[0] = fma(wud, d, M[0]);
+  M[3] += wud;
+  M[5] = fma(wu - wr, t, M[5]);
+}
+
 // FP64 bins.  e^{t} and e^{-t} are recomputed at each chunk start so their
 // product recurrences never run more than kChunk steps (relative error within
 // ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).  f at a node
 // is e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the
 // FP32 bins); even and odd nodes are summed apart (independent FMA chains).
-// DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums.
+// DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums,
+// taken about the centres ca (for t) and cb (for cosh t): the caller passes
+// the peak and its cosh, within a few widths of the integrand's means.
 template <int DER>
-__device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1) {
+__device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1,
+                                            double ca = 0.0, double cb = 1.0) {
   constexpr bool GRAD = DER >= 1;
   const double h = (t1 - t0) / (double)nb;
   const double Gs = G + kLn2;
@@ -398,7 +424,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   double u = 2.0 - r;
   BinSums s{};
   double S[2] = {0.0, 0.0}, Sv[2] = {0.0, 0.0}, Sx[2] = {0.0, 0.0};
-  double Svv[2] = {0.0, 0.0}, Sxx[2] = {0.0, 0.0}, Svx[2] = {0.0, 0.0};
+  double M[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // second-order moments (DER == 2)
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
@@ -415,11 +441,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
         const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
         Sv[b & 1] = fma(wr, t, Sv[b & 1]);
         Sx[b & 1] = fma(wu, ch, Sx[b & 1]);
-        if (DER >= 2) {
-          Svv[b & 1] = fma(wu * t, t, Svv[b & 1]);
-          Sxx[b & 1] = fma(wu * ch, ch, Sxx[b & 1]);
-          Svx[b & 1] = fma(wr * t, ch, Svx[b & 1]);
-        }
+        if (DER >= 2) moments(wu, wr, t, ch, ca, cb, M);
         r = fma(r, Q, E2);
       }
       u = fma(u, Q, E2);
@@ -439,11 +461,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
       const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
       Sv[m & 1] = fma(wr, t, Sv[m & 1]);
       Sx[m & 1] = fma(wu, ch, Sx[m & 1]);
-      if (DER >= 2) {
-        Svv[m & 1] = fma(wu * t, t, Svv[m & 1]);
-        Sxx[m & 1] = fma(wu * ch, ch, Sxx[m & 1]);
-        Svx[m & 1] = fma(wr * t, ch, Svx[m & 1]);
-      }
+      if (DER >= 2) moments(wu, wr, t, ch, ca, cb, M);
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -454,9 +472,12 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
     s.Sx = Sx[0] + Sx[1];
   }
   if (DER >= 2) {
-    s.Svv = Svv[0] + Svv[1];
-    s.Sxx = Sxx[0] + Sxx[1];
-    s.Svx = Svx[0] + Svx[1];
+    s.Svv = M[0];
+    s.Sxx = M[1];
+    s.Svx = M[2];
+    s.Sv1 = M[3];
+    s.Sx1 = M[4];
+    s.Sq = M[5];
   }
   return s;
 }

@@ -82,9 +82,20 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
 }
 
 // log K with its first and second derivatives in v and x from one pass over
-// the bins (Section 4.1, Eq. (13) with n + m <= 2):
-//   d2/dv2 log K = S_vv/S - (S_v/S)^2,  d2/dx2 log K = S_xx/S - (S_x/S)^2,
-//   d2/dvdx log K = -S_vx/S + (S_v/S)(S_x/S)   (odd in v, like d/dv).
+// the bins (Section 4.1, Eq. (13) with n + m <= 2).  Under the normalised
+// integrand p = f / K, with tau = tanh(v t) and C = cosh t,
+//   d2/dv2 log K = E[t^2] - E[t tau]^2,  d2/dx2 log K = Var C,
+//   d2/dvdx log K = -Cov(t tau, C)   (odd in v, like d/dv).
+// FP32 outputs form them from the raw sums (S_vv/S - (S_v/S)^2 and so on).
+// FP64 outputs take the sums about centres a = t_p and b = cosh t_p (the FP64
+// bins' moments): where the integrand is narrow (large v with small x, or
+// large x) E[C^2] exceeds Var C by up to ~1e8, and the raw difference would
+// lose that many digits.  With D = E[t] - a and Dx = E[C] - b from the
+// centred first moments,
+//   Var C = E[(C - b)^2] - Dx^2,  Cov(t tau, C) = E[t tau (C - b)] - E[t tau] Dx,
+//   E[t^2] - E[t tau]^2 = E[(t - a)^2] - D^2 + E[t - t tau] (E[t] + E[t tau]),
+// where E[t - t tau] = E[2 e^{-2vt} t / (1 + e^{-2vt})] comes from its own
+// positive sum, not as a difference of the two nearly equal means.
 // Every output is nullable.
 template <typename T, int NB>
 __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, const T* __restrict__ vin,
@@ -105,20 +116,36 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
   if (!domain_special(vs, x, lk, lv, lx)) {
     const double v = fabs(vs);
     const Bracket b = find_bracket(v, x, margin_of<T>());
-    const BinSums s = run_bins<T, 2>(nb, v, x, b);
-    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
     constexpr bool F64 = sizeof(T) == 8;
+    const double ca = (double)b.tp;  // centres of the FP64 moments
+    double cb = 1.0;
+    BinSums s;
+    if constexpr (F64) {
+      cb = cosh_f64(ca);
+      s = bins_f64<2>(nb, v, x, b.G, (double)b.t0, (double)b.t1, ca, cb);
+    } else {
+      s = bins_f32<2>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+    }
+    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
     // first order as bessel_logk_dv_dx (same operations, same results); the
-    // variances below lose digits to cancellation, so they take FP64 1/S0
+    // second order takes FP64 1/S0
     const double rS0o = rcp_of<F64>(s.S0);
     lk = b.G + log_of<F64>(h * s.S0);
     lv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0o, vs);
     lx = -s.Sx * rS0o;
     const double rS0 = rcp_f64(s.S0);
     const double ev = s.Sv * rS0, ex = s.Sx * rS0;
-    lvv = fma(-ev, ev, s.Svv * rS0);
-    lxx = fma(-ex, ex, s.Sxx * rS0);
-    const double mvx = fma(ev, ex, -s.Svx * rS0);  // any sign: flip it for v < 0, do not replace it
+    double mvx;  // -Cov(t tau, C), any sign: flip it for v < 0, do not replace it
+    if constexpr (F64) {
+      const double D = s.Sv1 * rS0, Dx = s.Sx1 * rS0;
+      lvv = fma(-D, D, s.Svv * rS0) + (s.Sq * rS0) * ((ca + D) + ev);
+      lxx = fma(-Dx, Dx, s.Sxx * rS0);
+      mvx = fma(ev, Dx, -s.Svx * rS0);
+    } else {
+      lvv = fma(-ev, ev, s.Svv * rS0);
+      lxx = fma(-ex, ex, s.Sxx * rS0);
+      mvx = fma(ev, ex, -s.Svx * rS0);
+    }
     lvx = (v == 0.0) ? 0.0 : (vs < 0.0 ? -mvx : mvx);
   }
   if (logk) logk[i] = (T)lk;

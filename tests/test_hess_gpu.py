@@ -1,15 +1,14 @@
 """GPU parity of the second derivatives of log K (bessel_logk_hess, through the
 C ABI) against the oracle, and second-order autograd.
 
-Tolerances (mixed error |got - ref| / max(1, |ref|)):
-  log K and first derivatives: the path's bars, FP64 1e-12, FP32 1e-5;
-  second derivatives: FP64 1e-10, FP32 1e-5.  d2/dv2 log K = S_vv/S - (S_v/S)^2
-  is a variance of t; where the integrand is narrow (large v, small x) the two
-  terms agree to ~4 digits (E[t^2] / Var t up to ~1e4), so the 1e-14 relative
-  error of each FP64 term becomes ~1e-10 of the difference; likewise for
-  d2/dx2 (a variance of cosh t) at large x.  In FP32 the sums are FP64 and the
-  nodes' FP32 exponentials perturb all sums alike, which leaves the
-  derivatives at the FP32 bar.
+Tolerances (mixed error |got - ref| / max(1, |ref|)): the path's bars, FP64
+1e-12 and FP32 1e-5, for log K and for the first and second derivatives.  The
+FP64 second derivatives are variances and a covariance under the normalised
+integrand (of t, t tanh(vt) and cosh t); the FP64 kernel forms them from
+moments about the peak, so they keep the bar where the integrand is narrow
+(large v with small x, or large x), where E[cosh^2 t] exceeds Var cosh t by up
+to ~1e8.  In FP32 the sums are FP64 and the nodes' FP32 exponentials perturb
+all sums alike, which leaves the raw differences at the FP32 bar.
 """
 
 import numpy as np
@@ -22,7 +21,7 @@ import workloads
 pytestmark = pytest.mark.gpu
 
 TOL1 = {torch.float64: 1e-12, torch.float32: 1e-5}
-TOL2 = {torch.float64: 1e-10, torch.float32: 1e-5}
+TOL2 = {torch.float64: 1e-12, torch.float32: 1e-5}
 
 
 @pytest.fixture(scope="module")
@@ -196,7 +195,8 @@ def test_second_order_autograd(bk):
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_validated_domain(bk, dt):
     # across the validated domain (v up to 1e3 and down to 1e-8, x in
-    # [1e-6, 1e5]); measured: FP64 first order <= 2e-14, second order <= 1.2e-11
-    # (d2/dvdx at v ~ 1e3, x ~ 3e-4); FP32 <= 1.5e-6
+    # [1e-6, 1e5]); the FP64 second derivatives were at 1.2e-11 (d2/dvdx at
+    # v ~ 1e3, x ~ 3e-4) when formed from raw moments
     v, x = workloads.domain_pairs(800, seed=61)
-    check_against_oracle(bk, v, x, dt)
+    err = check_against_oracle(bk, v, x, dt)
+    print(dt, "max mixed error per output", err.max(axis=0))
