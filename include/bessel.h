@@ -35,14 +35,15 @@
  *     x == +inf -> log K = -inf;  |v| == inf with finite x > 0 -> log K = +inf;
  *     derivatives are NaN in all of these.  v < 0 is evaluated at |v|
  *     (K_{-v} = K_v) with d/dv negated; v == 0 gives d/dv == 0 exactly.
- *     0 < x < 1e-36 -> NaN as well: below the range of the bracket search
- *     (which runs in FP32).
+ *     0 < x < 1e-36, finite x > 1e36 and finite |v| > 1e18 -> NaN as well:
+ *     beyond the range of the bracket search (which runs in FP32).
  *   - Validated domain (tests against the CPU oracle at the default 128 bins):
- *     |v| <= 1e3 with 1e-6 <= x <= 1e5 at the F64 bar (mixed error 1e-12) and
- *     1e-35 <= x <= 1e5 at the F32 bar (1e-5).  Outside it the results stay
+ *     |v| <= 1e3 with 1e-6 <= x <= 1e6 at the F64 bar (mixed error 1e-12) and
+ *     1e-35 <= x <= 1e6 at the F32 bar (1e-5).  Outside it the results stay
  *     finite but lose accuracy: below x ~ 1e-6 the bracket is so wide that 128
- *     bins resolve the d/dx integrand only to ~1e-10 (more bins restore it),
- *     and above x ~ 1e5 the FP32 bracket search rounds g(t_p) ~ -x.
+ *     bins resolve the d/dx integrand only to ~1e-10 (more bins restore it);
+ *     far above x ~ 1e6 the FP32 bracket search widens the bracket by the
+ *     FP32 rounding of g(t_p) ~ -x until 128 bins no longer resolve it.
  */
 #ifndef BESSEL_H
 #define BESSEL_H
@@ -160,17 +161,23 @@ int bessel_logdk(int dtype, int64_t n, const void* v, const void* x, int order_v
                  void* sign, int nbins, void* hip_stream);
 
 /*
- * bessel_set_split_threshold -- batch-size policy of bessel_logk and
- * bessel_logk_dv_dx on the Newton bracket.  Batches of at most n elements run
+ * bessel_set_split_threshold -- batch-size policy of bessel_logk,
+ * bessel_logk_dv_dx and bessel_logk_hess.  Batches of at most n elements run
  * kernels that give each element 16 lanes (every lane finds the bracket, sums
  * 1/16 of the bins, and the lanes add their FP64 partial sums): for small
  * batches, where one lane per element would leave most of the GPU idle, this
- * cuts the latency.  Larger batches run one lane per element.  The two
- * layouts add the same terms in a different order, so results can differ in
- * the last bits between them (both within the path's tolerance); for a given
- * n and threshold they are deterministic.  n = 0 turns the split kernels off.
- * Default 16384; at most BESSEL_MAX_SPLIT_THRESHOLD.  previous (nullable)
- * receives the old value.  Process-wide; takes effect for later calls.
+ * cuts the latency (Section 3.4 measures the time against the batch size).
+ * Larger batches run one lane per element.  The two layouts add the same
+ * terms in a different order, so results can differ in the last bits between
+ * them (both within the path's tolerance); for a given n and threshold they
+ * are deterministic.  bessel_logk and bessel_logk_dv_dx with a learned
+ * range_mode also take the Newton bracket on this layout for such batches (one
+ * launch; the predictor saves no time there), so their results equal those of
+ * BESSEL_RANGE_NEWTON and bessel_mlp_fallback_count reads 0 after them;
+ * bessel_range keeps the learned bracket at every size.  n = 0 turns the
+ * split kernels off.  Default 16384; at most BESSEL_MAX_SPLIT_THRESHOLD.
+ * previous (nullable) receives the old value.  Process-wide; takes effect for
+ * later calls.
  */
 #define BESSEL_MAX_SPLIT_THRESHOLD (1LL << 26)
 int bessel_set_split_threshold(int64_t n, int64_t* previous);
@@ -202,11 +209,14 @@ int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void*
 /*
  * Learned bracket predictor (FP32 path).
  *
- * A network 2 -> 64 -> 64 -> 2 (tanh) maps the features of an element,
+ * A network 2 -> 64 -> 64 -> 2 maps the features of an element,
  * ((log max(|v|, 1e-3) - m_v)/s_v, (log x - m_x)/s_x), to (y0, y1); the bracket
- * is t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1).  It is trained
- * on the method's own Newton brackets (Sections 2.2-2.3 at the FP32 eps), and
- * at inference (all three layers on bf16 MFMA with FP32 accumulation) every
+ * is t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1).  Its
+ * activations are tanh-shaped and need no transcendental: clamp(a, -1, 1) on
+ * the first layer, u (3 - u^2) / 2 with u = clamp(a / 1.5, -1, 1) on the second.
+ * It is trained on the method's own Newton brackets (Sections 2.2-2.3 at the
+ * FP32 eps), and at inference (all three layers on f16 MFMA with FP32
+ * accumulation, the activations in packed f16 arithmetic) every
  * predicted bracket is checked after the bins: the end terms must lie below eps
  * relative to the shift and the even-node and odd-node sums must agree to
  * 1e-5.  Elements that fail are recomputed by the Newton path in a second
@@ -214,7 +224,7 @@ int bessel_logk_backward(int dtype, int64_t n, const void* grad_out, const void*
  *
  * BESSEL_RANGE_MLP_TABLE reads the same network from a table: after each
  * change of the parameters, the first call in this mode evaluates the
- * network (the same bf16-MFMA inference) on a 256 x 256 grid of the feature
+ * network (the same f16-MFMA inference) on a 256 x 256 grid of the feature
  * plane, z in [-4, 4]^2, and stores per cell the bilinear coefficients of
  * both outputs (2.6 MB, owned by the handle). Each element then interpolates
  * the outputs of its cell instead of running 128 activations. Features
@@ -275,7 +285,7 @@ int bessel_mlp_loss_grad(bessel_mlp* mlp, int64_t n, const float* v, const float
 int bessel_mlp_adam_step(bessel_mlp* mlp, const float* grad, float lr, float beta1, float beta2, float eps,
                          void* hip_stream);
 /* Raw network outputs y[2 i], y[2 i + 1] for n device inputs; mode 0: FP32 with
- * exact tanh, one element per lane; mode 1: the bf16-MFMA inference of the
+ * the activations in FP32, one element per lane; mode 1: the f16-MFMA inference of the
  * fused kernel (the same operands and arithmetic); mode 2: the bilinear table
  * of BESSEL_RANGE_MLP_TABLE. */
 int bessel_mlp_forward(const bessel_mlp* mlp, int64_t n, const float* v, const float* x, float* y, int mode,
@@ -296,7 +306,12 @@ int bessel_mlp_fallback_count(const bessel_mlp* mlp, int* count);
  * path and its derivatives (Sections 2 and 4.1) and the chain rule.  Sums are
  * accumulated in FP64 and reduced in a fixed order (deterministic).  The call
  * allocates a temporary of nsets * ceil(nsamp/256) * 5 doubles, stream-ordered
- * on hip_stream.  range_mode must be BESSEL_RANGE_NEWTON.
+ * on hip_stream.  range_mode: BESSEL_RANGE_NEWTON (mlp ignored) or
+ * BESSEL_RANGE_MLP_TABLE (mlp required: the bracket from the predictor's
+ * table, checked after the bins as in bessel_logk; an element that fails the
+ * check takes the Newton bracket in the same pass, so no worklist is kept and
+ * the handle's fallback count is not changed).  BESSEL_RANGE_MLP returns
+ * BESSEL_ERR_UNSUPPORTED.
  */
 int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
                        int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam,
@@ -313,7 +328,9 @@ int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* alpha, cons
  * BESSEL_GH_NOALLOC_MAX_BLOCKS records, i.e. nsets * ceil(nsamp / 256) must not
  * exceed it (else BESSEL_ERR_ARG before any work is queued; 1024 sets of 65536
  * samples fit).  Each GPU the library runs on holds that array (10 MiB) until
- * the process ends; the first call on a GPU looks up its address there.  Every
+ * the process ends; the first call on a GPU looks up its address there.  With
+ * BESSEL_RANGE_MLP_TABLE the predictor's table is rebuilt, when its parameters
+ * changed, into buffers the handle allocated at creation.  Every
  * call on one GPU shares the array: calls that overlap in time on one GPU (on
  * different streams, or from different host threads) race and must be
  * serialised by the caller.  Nothing in the array needs clearing between calls.

@@ -5,9 +5,14 @@ The predictor maps the features of an element to its integration bracket
 range finder):
 
     features   z = ((log max(v, v_floor) - m_v) / s_v,  (log x - m_x) / s_x)
-    network    h1 = tanh(W1 z + b1)      W1: 64 x 2,  b1: 64
-               h2 = tanh(W2 h1 + b2)     W2: 64 x 64, b2: 64
-               y  = W3 h2 + b3           W3: 2 x 64,  b3: 2
+    network    h1 = clamp(W1 z + b1, -1, 1)   W1: 64 x 2,  b1: 64
+               h2 = phi(W2 h1 + b2)           W2: 64 x 64, b2: 64
+               y  = W3 h2 + b3                W3: 2 x 64,  b3: 2
+    activations  the clamp (derivative 1 inside, 0 outside) and
+               phi(a) = u (3 - u^2) / 2,  u = clamp(a / 1.5, -1, 1)
+               (a cubic sigmoid shaped like tanh: odd, phi'(0) = 1, constant
+               +-1 beyond |a| = 1.5, continuously differentiable), with
+               phi'(a) = 1 - u^2 inside and 0 outside
     targets    y0* = t0 / t1,  y1* = log t1
     loss       L = (1/B) sum_s 1/2 (w0 e0^2 + w1 e1^2),  e = y - y*,
                w0 = alpha if e0 > 0 else 1   (t0 predicted too large is unsafe)
@@ -56,14 +61,27 @@ def features(v, x, norm):
     return np.stack([(lv - norm[0]) / norm[1], (lx - norm[2]) / norm[3]], axis=1)
 
 
+ACT_C = 1.5
+
+
+def phi(a):
+    """The activation and its derivative, elementwise."""
+    u = np.clip(np.asarray(a, dtype=np.float64) / ACT_C, -1.0, 1.0)
+    return 0.5 * u * (3.0 - u * u), (1.5 / ACT_C) * (1.0 - u * u)
+
+
+def hard_clamp(a):
+    """The first layer's activation clamp(a, -1, 1) and its derivative."""
+    a = np.asarray(a, dtype=np.float64)
+    return np.clip(a, -1.0, 1.0), (np.abs(a) < 1.0).astype(np.float64)
+
+
 def forward(p, z):
     W1, b1, W2, b2, W3, b3 = unpack(p)
-    a1 = z @ W1.T + b1
-    h1 = np.tanh(a1)
-    a2 = h1 @ W2.T + b2
-    h2 = np.tanh(a2)
+    h1, d1 = hard_clamp(z @ W1.T + b1)
+    h2, d2 = phi(h1 @ W2.T + b2)
     y = h2 @ W3.T + b3
-    return y, (z, h1, h2)
+    return y, (z, h1, h2, d1, d2)
 
 
 def targets(t0, t1):
@@ -75,7 +93,7 @@ def targets(t0, t1):
 def loss_and_grad(p, z, ystar, alpha):
     """Mean asymmetric squared loss and its gradient with respect to p."""
     W1, b1, W2, b2, W3, b3 = unpack(p)
-    y, (z, h1, h2) = forward(p, z)
+    y, (z, h1, h2, d1, d2) = forward(p, z)
     B = z.shape[0]
     e = y - ystar
     w = np.ones_like(e)
@@ -85,10 +103,10 @@ def loss_and_grad(p, z, ystar, alpha):
     dy = w * e / B                      # B x 2
     gW3 = dy.T @ h2                     # 2 x 64
     gb3 = dy.sum(axis=0)
-    da2 = (dy @ W3) * (1.0 - h2 * h2)   # B x 64
+    da2 = (dy @ W3) * d2                # B x 64
     gW2 = da2.T @ h1                    # 64 x 64
     gb2 = da2.sum(axis=0)
-    da1 = (da2 @ W2) * (1.0 - h1 * h1)
+    da1 = (da2 @ W2) * d1
     gW1 = da1.T @ z                     # 64 x 2
     gb1 = da1.sum(axis=0)
     return L, pack(gW1, gb1, gW2, gb2, gW3, gb3)

@@ -183,9 +183,11 @@ def bessel_range(v: torch.Tensor, x: torch.Tensor, range: str = "newton", mlp=No
 
 def gh_logk_sum(lam: torch.Tensor, alpha: torch.Tensor, delta: torch.Tensor, mu: torch.Tensor, y: torch.Tensor,
                 grad_sum: torch.Tensor | None = None, nbins: int = 128, want_grad: bool = True,
-                no_alloc: bool = False):
+                no_alloc: bool = False, range: str = "newton", mlp=None):
     """Per-set sums of log K_{lam-1/2}(alpha sqrt(delta^2 + (y - mu)^2)) over the shared
     samples y, and (optionally) their gradients in (lam, alpha, delta, mu), FP32.
+    ``range``: "newton" or "mlp_table" (the predictor ``mlp`` read from its
+    table, checked per element, Newton bracket where the check fails).
     ``no_alloc`` calls ``bessel_gh_logk_sum_noalloc`` (partials in the library's
     static device array; calls on one GPU must not overlap)."""
     sets = [t.contiguous() for t in (lam, alpha, delta, mu)]
@@ -198,13 +200,14 @@ def gh_logk_sum(lam: torch.Tensor, alpha: torch.Tensor, delta: torch.Tensor, mu:
         raise ValueError("lam, alpha, delta, mu (and grad_sum) must have the same length")
     dev = y.device
     out = torch.empty(n, dtype=torch.float32, device=dev)
-    grads = [torch.empty(n, dtype=torch.float32, device=dev) for _ in range(4)] if want_grad else [None] * 4
+    grads = ([torch.empty(n, dtype=torch.float32, device=dev) for _ in (0, 1, 2, 3)] if want_grad
+             else [None] * 4)
     gs = grad_sum.contiguous() if grad_sum is not None else None
     lib = load()
     with _on(dev):
         fn = lib.bessel_gh_logk_sum_noalloc if no_alloc else lib.bessel_gh_logk_sum
         rc = fn(n, *(_ptr(t) for t in sets), y.numel(), _ptr(y), _ptr(gs), _ptr(out), *(_ptr(g) for g in grads),
-                int(nbins), RANGE_NEWTON, ctypes.c_void_p(0), _stream_ptr(dev))
+                int(nbins), _range_code(range), _mlp_ptr(mlp), _stream_ptr(dev))
     check(rc, "bessel_gh_logk_sum_noalloc" if no_alloc else "bessel_gh_logk_sum")
     return (out, *grads) if want_grad else out
 

@@ -183,6 +183,29 @@ __device__ __forceinline__ double g_f64(double v, double x, double t) {
   return log_cosh_f64(v * t) - x * cosh_f64(t);
 }
 
+// e^t - 1 and 1 - e^{-t} for t >= 0, each to a few ulp relative (also as
+// t -> 0); their product is 2 (cosh t - 1).
+struct Expm1Pair {
+  double ep, em;  // e^t - 1 and 1 - e^{-t}
+};
+
+__device__ __forceinline__ Expm1Pair expm1_pair(double t) {
+  const ExpParts e = exp_parts(t);
+  const double m = (e.k == 0) ? e.em1 : scale2k(1.0 + e.em1, e.k) - 1.0;  // e^t >= e^{ln2/2} when k > 0
+  return {m, m * rcp_f64(1.0 + m)};
+}
+
+__device__ __forceinline__ double coshm1_f64(double t) {
+  const Expm1Pair p = expm1_pair(t);
+  return 0.5 * (p.ep * p.em);
+}
+
+// g(t) + x = log cosh(v t) - x (cosh t - 1), without the cancellation of
+// x cosh t against x for large x.
+__device__ __forceinline__ double g_plus_x_f64(double v, double x, double t) {
+  return log_cosh_f64(v * t) - x * coshm1_f64(t);
+}
+
 // log cosh z for z >= 0, FP32 hardware form (absolute error ~1e-7 |z|).
 __device__ __forceinline__ float log_cosh_f32(float z) {
   const float q = hexp2(-2.0f * kLog2eF * z);
@@ -190,15 +213,22 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
 }
 
 // Domain conventions (see include/bessel.h).  Returns true when the element is
-// outside v real, 0 < x < inf; then logk, dv, dx hold the convention's values.
-// Smallest x the FP32 bracket search can represent: the upper end solves
-// x cosh t = L with L up to ~37 (FP64 margin), so L / x must stay below the
-// FP32 maximum.  Smaller positive x gives NaN (documented in the header).
+// outside v real, 0 < x < inf, or outside the range the FP32 bracket search
+// represents; then logk, dv, dx hold the convention's values.
+// Smallest x: the upper end solves x cosh t = L with L up to ~37 (FP64
+// margin), so L / x must stay below the FP32 maximum.  Largest x: x itself
+// and g(t_p) ~ -x must stay well inside the FP32 range.  Largest |v|: the peak
+// search forms v^2 in FP32.  Finite inputs beyond these give NaN (documented
+// in the header), as do NaN inputs and x < 0.
 constexpr double kMinX = 1e-36;
+constexpr double kMaxX = 1e36;
+constexpr double kMaxV = 1e18;
 
 __device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
   const double nan_ = __builtin_nan("");
-  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0 || (x > 0.0 && x < kMinX)) {
+  const bool beyond = (x > 0.0 && x < kMinX) || (x > kMaxX && !__builtin_isinf(x)) ||
+                      (fabs(v) > kMaxV && !__builtin_isinf(v));
+  if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0 || beyond) {
     logk = nan_; dv = nan_; dx = nan_;
     return true;
   }
@@ -238,6 +268,7 @@ __device__ __forceinline__ double rcp_of(double y) {
 // ---------------------------------------------------------------------------
 struct Bracket {
   double G;    // g(t_p), FP64
+  double Gx;   // g(t_p) + x, FP64 without cancellation (the FP64 bins' shift)
   float tp;    // peak location (at or to the right of the true peak)
   float t0;    // lower end (0, or at/left of the crossing)
   float t1;    // upper end (at/right of the crossing)
@@ -333,11 +364,13 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
   const float lx = hlog2(xf);
   float tp = 0.0f;
   if (v * v > x) tp = peak_f32(vf, xf, lx);
-  const double G = g_f64(v, x, (double)tp);
+  const double Gx = g_plus_x_f64(v, x, (double)tp);
+  const double G = Gx - x;
   const float Gf = (float)G;
   const float xcp = hexp2(fmaf(kLog2eF, tp, lx)) + hexp2(fmaf(-kLog2eF, tp, lx));  // 2 x cosh t_p
   const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + xcp);
   b.G = G;
+  b.Gx = Gx;
   b.tp = tp;
   b.t1 = upper_f32(vf, xf, lx, tp, Gf, L);
   const bool need_t0 = (-x - G + (double)L) <= 0.0;
@@ -386,7 +419,8 @@ constexpr int kChunk = 16;    // nodes per unrolled chunk (FP64 bins)
 constexpr int kChunk32 = 32;  // nodes per unrolled chunk (FP32 bins)
 
 // Second-order moments of one FP64 node (DER == 2), about the centres a (t)
-// and b (cosh t): with wu = e^{A} u (f) and wr = e^{A} r (d/dv f / t),
+// and b (cosh t; C and b may both be given less 1): with wu = e^{A} u (f) and
+// wr = e^{A} r (d/dv f / t),
 //   M0 += wu (t - a)^2,  M1 += wu (C - b)^2,  M2 += wr t (C - b),
 //   M3 += wu (t - a),    M4 += wu (C - b),    M5 += (wu - wr) t.
 // Six sums, 12 operations a node against 6 for the raw moments t^2 f,
@@ -402,22 +436,31 @@ __device__ __forceinline__ void moments(double wu, double wr, double t, double C
   M[5] = fma(wu - wr, t, M[5]);
 }
 
-// FP64 bins.  e^{t} and e^{-t} are recomputed at each chunk start so their
-// product recurrences never run more than kChunk steps (relative error within
-// ~kChunk ulp, which keeps x cosh t accurate to ~1e-15 relative).  f at a node
-// is e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the
-// FP32 bins); even and odd nodes are summed apart (independent FMA chains).
+// FP64 bins.  The argument of a node's exponential is formed relative to
+// g(t_p) + x: A - G = v t - x (cosh t - 1) - (g(t_p) + x) - log 2, so that for
+// large x (where g(t_p) ~ -x and cosh t ~ 1 across the bracket) no term of
+// size x cancels.  cosh t - 1 = (e^t - 1)(1 - e^{-t}) / 2, a product of two
+// positive factors, each by a recurrence with positive terms:
+//   e^{t+h} - 1 = (e^t - 1) e^h + (e^h - 1),
+//   1 - e^{-(t+h)} = (1 - e^{-t}) e^{-h} + (1 - e^{-h}),
+// (relative error within ~m ulp after m steps, also as t -> 0), both
+// recomputed at each chunk start (every kChunk nodes).  f at a node is
+// e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the FP32
+// bins); even and odd nodes are summed apart (independent FMA chains).
+// S_x = sum f cosh t is returned as S0 + sum f (cosh t - 1).
 // DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums,
-// taken about the centres ca (for t) and cb (for cosh t): the caller passes
-// the peak and its cosh, within a few widths of the integrand's means.
+// taken about the centres ca (for t) and 1 + cb1 (for cosh t): the caller
+// passes the peak and its cosh - 1, within a few widths of the integrand's
+// means.  Gx = g(t_p) + x without cancellation (Bracket::Gx).
 template <int DER>
-__device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G, double t0, double t1,
-                                            double ca = 0.0, double cb = 1.0) {
+__device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double Gx, double t0, double t1,
+                                            double ca = 0.0, double cb1 = 0.0) {
   constexpr bool GRAD = DER >= 1;
   const double h = (t1 - t0) / (double)nb;
-  const double Gs = G + kLn2;
+  const double Gs = Gx + kLn2;
   const double xh = 0.5 * x;
-  const double eh = exp_f64(h), ehi = rcp_f64(eh);
+  const Expm1Pair hh = expm1_pair(h);
+  const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
   const double Q = exp_f64(-2.0 * v * h);
   const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
@@ -428,40 +471,39 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
-    double E = exp_f64(ta);
-    double Ei = rcp_f64(E);
+    Expm1Pair an = expm1_pair(ta);
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
       const double t = fma((double)b, h, ta);
-      const double ch2 = E + Ei;
-      double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+      const double P = an.ep * an.em;  // 2 (cosh t - 1)
+      double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
       if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
       S[b & 1] = fma(w, u, S[b & 1]);
       if (GRAD) {
-        const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
+        const double wr = w * r, wu = w * u;
         Sv[b & 1] = fma(wr, t, Sv[b & 1]);
-        Sx[b & 1] = fma(wu, ch, Sx[b & 1]);
-        if (DER >= 2) moments(wu, wr, t, ch, ca, cb, M);
+        Sx[b & 1] = fma(wu, P, Sx[b & 1]);
+        if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
         r = fma(r, Q, E2);
       }
       u = fma(u, Q, E2);
-      E *= eh;
-      Ei *= ehi;
+      an.ep = fma(an.ep, eh, hh.ep);
+      an.em = fma(an.em, ehi, hh.em);
     }
   }
   // remainder nodes (nb not a multiple of kChunk) and the last node m = nb
   for (int m = nchunks * kChunk; m <= nb; ++m) {
     const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-    const double E = exp_f64(t);
-    const double ch2 = E + rcp_f64(E);
-    double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    const Expm1Pair an = expm1_pair(t);
+    const double P = an.ep * an.em;
+    double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
     if (m == 0 || m == nb) w *= 0.5;
     S[m & 1] = fma(w, u, S[m & 1]);
     if (GRAD) {
-      const double wr = w * r, wu = w * u, ch = 0.5 * ch2;
+      const double wr = w * r, wu = w * u;
       Sv[m & 1] = fma(wr, t, Sv[m & 1]);
-      Sx[m & 1] = fma(wu, ch, Sx[m & 1]);
-      if (DER >= 2) moments(wu, wr, t, ch, ca, cb, M);
+      Sx[m & 1] = fma(wu, P, Sx[m & 1]);
+      if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -469,7 +511,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   s.S0 = S[0] + S[1];
   if (GRAD) {
     s.Sv = Sv[0] + Sv[1];
-    s.Sx = Sx[0] + Sx[1];
+    s.Sx = fma(0.5, Sx[0] + Sx[1], s.S0);
   }
   if (DER >= 2) {
     s.Svv = M[0];
@@ -633,8 +675,14 @@ __device__ __forceinline__ BinSums sub_bins_f32(int nb, int m_lo, int m_hi, bool
     s.S0 = fma(wd, u, s.S0);
     if (GRAD) {
       const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-      s.Sv = fma(wd * r, t, s.Sv);
-      s.Sx = fma(wd * u, C, s.Sx);
+      const double wr = wd * r, wu = wd * u;
+      s.Sv = fma(wr, t, s.Sv);
+      s.Sx = fma(wu, C, s.Sx);
+      if (DER >= 2) {
+        s.Svv = fma(wu * t, t, s.Svv);
+        s.Sxx = fma(wu * C, C, s.Sxx);
+        s.Svx = fma(wr * t, C, s.Svx);
+      }
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -648,37 +696,50 @@ __device__ __forceinline__ BinSums sub_bins_f32(int nb, int m_lo, int m_hi, bool
 
 template <int DER>
 __device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool with_end, double v, double x,
-                                                double G, double t0, double t1) {
+                                                double Gx, double t0, double t1, double ca = 0.0, double cb1 = 0.0) {
   constexpr bool GRAD = DER >= 1;
   const double h = (t1 - t0) / (double)nb;
-  const double Gs = G + kLn2;
+  const double Gs = Gx + kLn2;
   const double xh = 0.5 * x;
-  const double eh = exp_f64(h), ehi = rcp_f64(eh);
+  const Expm1Pair hh = expm1_pair(h);
+  const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
   const double Q = exp_f64(-2.0 * v * h);
   const double E2 = one_minus_exp_neg(2.0 * v * h);
   double r = one_minus_exp_neg(2.0 * v * fma((double)m_lo, h, t0));
   double u = 2.0 - r;
-  double E = 0.0, Ei = 0.0;
+  Expm1Pair an{0.0, 0.0};
+  double M[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};  // second-order moments (DER == 2)
+  double SxP = 0.0;
   BinSums s{};
   for (int m = m_lo; m <= m_hi; ++m) {
     if (m == m_hi && !with_end) break;
     const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-    if ((m - m_lo) % kChunk == 0 || m == nb) {  // products re-anchored every kChunk nodes
-      E = exp_f64(t);
-      Ei = rcp_f64(E);
-    }
-    const double ch2 = E + Ei;
-    double w = exp_node_f64(fma(-xh, ch2, fma(v, t, -Gs)));
+    if ((m - m_lo) % kChunk == 0 || m == nb) an = expm1_pair(t);  // recurrences re-anchored every kChunk nodes
+    const double P = an.ep * an.em;  // 2 (cosh t - 1)
+    double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
     if (m == 0 || m == nb) w *= 0.5;
     s.S0 = fma(w, u, s.S0);
     if (GRAD) {
-      s.Sv = fma(w * r, t, s.Sv);
-      s.Sx = fma(w * u, 0.5 * ch2, s.Sx);
+      const double wr = w * r, wu = w * u;
+      s.Sv = fma(wr, t, s.Sv);
+      SxP = fma(wu, P, SxP);
+      if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
-    E *= eh;
-    Ei *= ehi;
+    an.ep = fma(an.ep, eh, hh.ep);
+    an.em = fma(an.em, ehi, hh.em);
+  }
+  // S_x = sum f cosh t as the sum of f and of f (cosh t - 1): the split kernels
+  // add each lane's S0 and Sx over the group, so Sx carries both parts
+  if (GRAD) s.Sx = fma(0.5, SxP, s.S0);
+  if (DER >= 2) {
+    s.Svv = M[0];
+    s.Sxx = M[1];
+    s.Svx = M[2];
+    s.Sv1 = M[3];
+    s.Sx1 = M[4];
+    s.Sq = M[5];
   }
   return s;
 }

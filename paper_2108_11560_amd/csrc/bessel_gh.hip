@@ -21,6 +21,7 @@
 #include "bessel.h"
 #include "bessel_device.hpp"
 #include "bessel_internal.hpp"
+#include "bessel_learned.hpp"
 
 namespace bk {
 
@@ -33,11 +34,15 @@ __device__ __forceinline__ double wave_sum(double a) {
   return a;
 }
 
-template <int NB>
+// TAB: the bracket from the network's table (range mode BESSEL_RANGE_MLP_TABLE;
+// Q, cells: the handle's operands), checked after its bins; an element whose
+// learned bracket fails the check takes the Newton bracket in the same lane.
+template <int NB, bool TAB>
 __global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nchunks, int nbins,
                                                        const float* __restrict__ lam, const float* __restrict__ alpha,
                                                        const float* __restrict__ delta, const float* __restrict__ mu,
-                                                       const float* __restrict__ y, double* __restrict__ partial) {
+                                                       const float* __restrict__ y, const float* __restrict__ Q,
+                                                       const float4* __restrict__ cells, double* __restrict__ partial) {
   __shared__ double red[kBlock / 64][kGhQ];
   const int64_t set = (int64_t)blockIdx.x / nchunks;
   const int64_t chunk = (int64_t)blockIdx.x - set * nchunks;
@@ -53,11 +58,25 @@ __global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nc
     double lk, dv, dx;
     if (!domain_special(vs, x, lk, dv, dx)) {
       const double v = fabs(vs);
-      const Bracket b = find_bracket(v, x, kMarginGh);
-      const BinSums s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
-      const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+      BinSums s;
+      double G = 0.0, t0 = 0.0, t1 = 0.0;
+      bool ok = false;
+      if constexpr (TAB) {
+        float z0, z1, y0, y1;
+        mlp_features_q(Q, (float)v, (float)x, z0, z1);
+        mlp_table(cells, z0, z1, y0, y1);
+        LearnedBracket lb;
+        ok = learned_bins<1>(Q, v, x, y0, y1, nb, lb, s);
+        G = (double)lb.G, t0 = (double)lb.t0, t1 = (double)lb.t1;
+      }
+      if (!ok) {
+        const Bracket b = find_bracket(v, x, kMarginGh);
+        s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+        G = b.G, t0 = (double)b.t0, t1 = (double)b.t1;
+      }
+      const double h = (t1 - t0) / (double)nb;
       const double rS0 = rcp_of<false>(s.S0);
-      lk = b.G + log_of<false>(h * s.S0);
+      lk = G + log_of<false>(h * s.S0);
       dv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0, vs);
       dx = -s.Sx * rS0;
     }
@@ -149,12 +168,15 @@ namespace {
 // (set, chunk) blocks, i.e. of partial records the call needs.
 int gh_checks(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
               int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam, float* g_alpha,
-              float* g_delta, float* g_mu, int nbins, int range_mode, int64_t& nchunks, int64_t& nblocks) {
+              float* g_delta, float* g_mu, int nbins, int range_mode, const bessel_mlp* mlp, int64_t& nchunks,
+              int64_t& nblocks) {
   if (nsets < 0 || nsamp < 0) return set_error(BESSEL_ERR_ARG, "nsets and nsamp must be >= 0");
-  if (range_mode != BESSEL_RANGE_NEWTON)
-    return set_error(range_mode == BESSEL_RANGE_MLP || range_mode == BESSEL_RANGE_MLP_TABLE ? BESSEL_ERR_UNSUPPORTED
-                                                                                         : BESSEL_ERR_RANGE_MODE,
-                     "the per-set sums use the Newton bracket");
+  if (range_mode == BESSEL_RANGE_MLP)
+    return set_error(BESSEL_ERR_UNSUPPORTED, "the per-set sums take the Newton bracket or the network's table");
+  if (range_mode != BESSEL_RANGE_NEWTON && range_mode != BESSEL_RANGE_MLP_TABLE)
+    return set_error(BESSEL_ERR_RANGE_MODE, "unknown range_mode %d", range_mode);
+  if (range_mode == BESSEL_RANGE_MLP_TABLE && !mlp)
+    return set_error(BESSEL_ERR_RANGE_MODE, "BESSEL_RANGE_MLP_TABLE needs an mlp");
   if (nbins < BESSEL_MIN_BINS || nbins > BESSEL_MAX_BINS)
     return set_error(BESSEL_ERR_NBINS, "nbins = %d outside [%d, %d]", nbins, BESSEL_MIN_BINS, BESSEL_MAX_BINS);
   nchunks = nsamp > 0 ? (nsamp + kBlock - 1) / kBlock : 1;
@@ -177,19 +199,43 @@ int gh_checks(int64_t nsets, const float* lam, const float* alpha, const float* 
   return BESSEL_OK;
 }
 
+template <bool TAB>
+void gh_partials(dim3 grid, hipStream_t st, int64_t nsamp, int64_t nchunks, int nbins, const float* lam,
+                 const float* alpha, const float* delta, const float* mu, const float* y, const float* Q,
+                 const float4* cells, double* partial) {
+  switch (nbins) {
+    case 64:
+      k_gh_partial<64, TAB><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, Q, cells, partial);
+      break;
+    case 128:
+      k_gh_partial<128, TAB><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, Q, cells, partial);
+      break;
+    case 256:
+      k_gh_partial<256, TAB><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, Q, cells, partial);
+      break;
+    default:
+      k_gh_partial<0, TAB><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, Q, cells, partial);
+      break;
+  }
+}
+
 // The two kernels of a call, with the partial records at `partial`
 // (nblocks * kGhQ doubles, every one written by k_gh_partial before
-// k_gh_final reads it, so nothing needs clearing).
+// k_gh_final reads it, so nothing needs clearing).  With the table range the
+// handle's operands are refreshed first (kernel launches only).
 int gh_launch(int64_t nsets, const float* lam, const float* alpha, const float* delta, const float* mu,
               int64_t nsamp, const float* y, const float* grad_sum, float* sum, float* g_lam, float* g_alpha,
-              float* g_delta, float* g_mu, int nbins, int64_t nchunks, int64_t nblocks, double* partial,
-              hipStream_t st) {
+              float* g_delta, float* g_mu, int nbins, int range_mode, const bessel_mlp* mlp, int64_t nchunks,
+              int64_t nblocks, double* partial, hipStream_t st) {
   const dim3 grid((unsigned)nblocks);
-  switch (nbins) {
-    case 64: k_gh_partial<64><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
-    case 128: k_gh_partial<128><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
-    case 256: k_gh_partial<256><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
-    default: k_gh_partial<0><<<grid, kBlock, 0, st>>>(nsamp, nchunks, nbins, lam, alpha, delta, mu, y, partial); break;
+  if (range_mode == BESSEL_RANGE_MLP_TABLE) {
+    const float* Q = nullptr;
+    const float4* cells = nullptr;
+    const int rc = mlp_table_operands(mlp, st, &Q, &cells);
+    if (rc) return rc;
+    gh_partials<true>(grid, st, nsamp, nchunks, nbins, lam, alpha, delta, mu, y, Q, cells, partial);
+  } else {
+    gh_partials<false>(grid, st, nsamp, nchunks, nbins, lam, alpha, delta, mu, y, nullptr, nullptr, partial);
   }
   int rc = check_launch("k_gh_partial");
   if (rc) return rc;
@@ -208,17 +254,16 @@ extern "C" int bessel_gh_logk_sum(int64_t nsets, const float* lam, const float* 
                                   const float* mu, int64_t nsamp, const float* y, const float* grad_sum, float* sum,
                                   float* g_lam, float* g_alpha, float* g_delta, float* g_mu, int nbins,
                                   int range_mode, const bessel_mlp* mlp, void* hip_stream) {
-  (void)mlp;
   int64_t nchunks = 0, nblocks = 0;
   int rc = gh_checks(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
-                     range_mode, nchunks, nblocks);
+                     range_mode, mlp, nchunks, nblocks);
   if (rc || nsets == 0) return rc;
   hipStream_t st = (hipStream_t)hip_stream;
   double* partial = nullptr;
   hipError_t e = hipMallocAsync((void**)&partial, (size_t)nblocks * kGhQ * sizeof(double), st);
   if (e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
-  rc = gh_launch(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins, nchunks,
-                 nblocks, partial, st);
+  rc = gh_launch(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
+                 range_mode, mlp, nchunks, nblocks, partial, st);
   e = hipFreeAsync(partial, st);
   if (rc == BESSEL_OK && e != hipSuccess) return set_error(BESSEL_ERR_HIP, "partials: %s", hipGetErrorString(e));
   return rc;
@@ -228,10 +273,9 @@ extern "C" int bessel_gh_logk_sum_noalloc(int64_t nsets, const float* lam, const
                                           const float* mu, int64_t nsamp, const float* y, const float* grad_sum,
                                           float* sum, float* g_lam, float* g_alpha, float* g_delta, float* g_mu,
                                           int nbins, int range_mode, const bessel_mlp* mlp, void* hip_stream) {
-  (void)mlp;
   int64_t nchunks = 0, nblocks = 0;
   int rc = gh_checks(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
-                     range_mode, nchunks, nblocks);
+                     range_mode, mlp, nchunks, nblocks);
   if (rc || nsets == 0) return rc;
   if (nblocks > kGhScratchBlocks)
     return set_error(BESSEL_ERR_ARG, "nsets x ceil(nsamp / %d) = %lld exceeds the %lld records of the static partials",
@@ -241,5 +285,5 @@ extern "C" int bessel_gh_logk_sum_noalloc(int64_t nsets, const float* lam, const
   rc = gh_scratch(st, &partial);
   if (rc) return rc;
   return gh_launch(nsets, lam, alpha, delta, mu, nsamp, y, grad_sum, sum, g_lam, g_alpha, g_delta, g_mu, nbins,
-                   nchunks, nblocks, partial, st);
+                   range_mode, mlp, nchunks, nblocks, partial, st);
 }

@@ -21,9 +21,14 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes);
 int check_launch(const char* what);
 int grid_for(int64_t n, dim3& grid);
 
-// Plain Newton-range paths (bessel_kernels.hip).
+// Plain Newton-range paths (bessel_kernels.hip).  clear (nullable): a device
+// counter the first thread sets to 0; force_split: the kSplit-lanes layout
+// whatever the batch-size policy says.
 int logk_newton(int dtype, int64_t n, const void* v, const void* x, const void* go, void* lk, void* dv, void* dx,
-                int nbins, bool grad, hipStream_t st);
+                int nbins, bool grad, hipStream_t st, int* clear = nullptr, bool force_split = false);
+// The batch-size policy: batches of at most this many elements take the
+// kSplit-lanes layouts (bessel_set_split_threshold).
+int64_t split_threshold();
 int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1, void* tp, void* gpk,
                  hipStream_t st);
 
@@ -31,6 +36,9 @@ int range_newton(int dtype, int64_t n, const void* v, const void* x, void* t0, v
 // table: the network's bilinear table instead of its per-element inference.
 int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
              bool grad, const bessel_mlp* mlp, bool table, hipStream_t st);
+// The handle's packed inference operands and its network table, rebuilt on
+// st first if the parameters changed (kernel launches only, no allocation).
+int mlp_table_operands(const bessel_mlp* mlp, hipStream_t st, const float** Q, const float4** cells);
 int range_mlp(int64_t n, const float* v, const float* x, float* t0, float* t1, float* tp, float* gpk,
               uint8_t* fallback, const bessel_mlp* mlp, bool table, hipStream_t st);
 

@@ -32,7 +32,7 @@ __device__ __forceinline__ float margin_of() {
 template <typename T, int DER>
 __device__ __forceinline__ BinSums run_bins(int nb, double v, double x, const Bracket& b) {
   if constexpr (sizeof(T) == 8) {
-    return bins_f64<DER>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
+    return bins_f64<DER>(nb, v, x, b.Gx, (double)b.t0, (double)b.t1);
   } else {
     return bins_f32<DER>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
   }
@@ -88,7 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
 //   d2/dvdx log K = -Cov(t tau, C)   (odd in v, like d/dv).
 // FP32 outputs form them from the raw sums (S_vv/S - (S_v/S)^2 and so on).
 // FP64 outputs take the sums about centres a = t_p and b = cosh t_p (the FP64
-// bins' moments): where the integrand is narrow (large v with small x, or
+// bins' moments, of cosh t - 1 about cosh t_p - 1): where the integrand is narrow (large v with small x, or
 // large x) E[C^2] exceeds Var C by up to ~1e8, and the raw difference would
 // lose that many digits.  With D = E[t] - a and Dx = E[C] - b from the
 // centred first moments,
@@ -97,6 +97,35 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
 // where E[t - t tau] = E[2 e^{-2vt} t / (1 + e^{-2vt})] comes from its own
 // positive sum, not as a difference of the two nearly equal means.
 // Every output is nullable.
+// The six outputs of k_logk_hess from an element's bracket and sums (the
+// bracket's t_p is the centre of the FP64 moments).
+template <bool F64>
+__device__ __forceinline__ void hess_outputs(double vs, double v, const Bracket& b, const BinSums& s, int nb,
+                                             double& lk, double& lv, double& lx, double& lvv, double& lxx,
+                                             double& lvx) {
+  const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
+  // first order as bessel_logk_dv_dx (same operations, same results); the
+  // second order takes FP64 1/S0
+  const double rS0o = rcp_of<F64>(s.S0);
+  lk = b.G + log_of<F64>(h * s.S0);
+  lv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0o, vs);
+  lx = -s.Sx * rS0o;
+  const double rS0 = rcp_f64(s.S0);
+  const double ev = s.Sv * rS0, ex = s.Sx * rS0;
+  double mvx;  // -Cov(t tau, C), any sign: flip it for v < 0, do not replace it
+  if constexpr (F64) {
+    const double D = s.Sv1 * rS0, Dx = s.Sx1 * rS0;
+    lvv = fma(-D, D, s.Svv * rS0) + (s.Sq * rS0) * (((double)b.tp + D) + ev);
+    lxx = fma(-Dx, Dx, s.Sxx * rS0);
+    mvx = fma(ev, Dx, -s.Svx * rS0);
+  } else {
+    lvv = fma(-ev, ev, s.Svv * rS0);
+    lxx = fma(-ex, ex, s.Sxx * rS0);
+    mvx = fma(ev, ex, -s.Svx * rS0);
+  }
+  lvx = (v == 0.0) ? 0.0 : (vs < 0.0 ? -mvx : mvx);
+}
+
 template <typename T, int NB>
 __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, const T* __restrict__ vin,
                                                       const T* __restrict__ xin, T* __restrict__ logk,
@@ -117,36 +146,14 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
     const double v = fabs(vs);
     const Bracket b = find_bracket(v, x, margin_of<T>());
     constexpr bool F64 = sizeof(T) == 8;
-    const double ca = (double)b.tp;  // centres of the FP64 moments
-    double cb = 1.0;
     BinSums s;
     if constexpr (F64) {
-      cb = cosh_f64(ca);
-      s = bins_f64<2>(nb, v, x, b.G, (double)b.t0, (double)b.t1, ca, cb);
+      const double ca = (double)b.tp;  // centres of the FP64 moments
+      s = bins_f64<2>(nb, v, x, b.Gx, (double)b.t0, (double)b.t1, ca, coshm1_f64(ca));
     } else {
       s = bins_f32<2>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
     }
-    const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
-    // first order as bessel_logk_dv_dx (same operations, same results); the
-    // second order takes FP64 1/S0
-    const double rS0o = rcp_of<F64>(s.S0);
-    lk = b.G + log_of<F64>(h * s.S0);
-    lv = (v == 0.0) ? 0.0 : copysign(s.Sv * rS0o, vs);
-    lx = -s.Sx * rS0o;
-    const double rS0 = rcp_f64(s.S0);
-    const double ev = s.Sv * rS0, ex = s.Sx * rS0;
-    double mvx;  // -Cov(t tau, C), any sign: flip it for v < 0, do not replace it
-    if constexpr (F64) {
-      const double D = s.Sv1 * rS0, Dx = s.Sx1 * rS0;
-      lvv = fma(-D, D, s.Svv * rS0) + (s.Sq * rS0) * ((ca + D) + ev);
-      lxx = fma(-Dx, Dx, s.Sxx * rS0);
-      mvx = fma(ev, Dx, -s.Svx * rS0);
-    } else {
-      lvv = fma(-ev, ev, s.Svv * rS0);
-      lxx = fma(-ex, ex, s.Sxx * rS0);
-      mvx = fma(ev, ex, -s.Svx * rS0);
-    }
-    lvx = (v == 0.0) ? 0.0 : (vs < 0.0 ? -mvx : mvx);
+    hess_outputs<F64>(vs, v, b, s, nb, lk, lv, lx, lvv, lxx, lvx);
   }
   if (logk) logk[i] = (T)lk;
   if (dv) dv[i] = (T)lv;
@@ -169,15 +176,18 @@ __device__ __forceinline__ double group_sum(double a) {
   return a;
 }
 
+// clear (nullable): a counter set to 0 by the first thread (the worklist count
+// of a learned-range handle whose small call runs here).
 template <typename T, int NB, bool GRAD>
 __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, const T* __restrict__ vin,
                                                        const T* __restrict__ xin, const T* __restrict__ gout,
                                                        T* __restrict__ logk, T* __restrict__ dv,
-                                                       T* __restrict__ dx) {
+                                                       T* __restrict__ dx, int* __restrict__ clear) {
   if constexpr (sizeof(T) == 8) {
     exp2_table_init();
     __syncthreads();
   }
+  if (clear && blockIdx.x == 0 && threadIdx.x == 0) *clear = 0;
   const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kSplit;
   const int k = (int)(threadIdx.x % kSplit);
   const bool in = e < n;
@@ -193,7 +203,7 @@ __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, con
     b = find_bracket(v, x, margin_of<T>());
     const int m_lo = (k * nb) / kSplit, m_hi = ((k + 1) * nb) / kSplit;
     if constexpr (sizeof(T) == 8)
-      s = sub_bins_f64<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.G, (double)b.t0, (double)b.t1);
+      s = sub_bins_f64<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.Gx, (double)b.t0, (double)b.t1);
     else
       s = sub_bins_f32<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.G, (double)b.t0, (double)b.t1);
   }
@@ -223,6 +233,64 @@ __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, con
   } else {
     logk[e] = (T)lk;
   }
+}
+
+// Second derivatives for small batches: the layout of k_logk_split (kSplit
+// lanes per element, each summing 1/kSplit of the nodes; the group adds its
+// FP64 partial sums with butterfly shuffles) with the sums of k_logk_hess.
+template <typename T, int NB>
+__global__ __launch_bounds__(kBlock) void k_logk_hess_split(int64_t n, int nbins, const T* __restrict__ vin,
+                                                            const T* __restrict__ xin, T* __restrict__ logk,
+                                                            T* __restrict__ dv, T* __restrict__ dx,
+                                                            T* __restrict__ dvv, T* __restrict__ dxx,
+                                                            T* __restrict__ dvx) {
+  if constexpr (sizeof(T) == 8) {
+    exp2_table_init();
+    __syncthreads();
+  }
+  constexpr bool F64 = sizeof(T) == 8;
+  const int64_t e = ((int64_t)blockIdx.x * kBlock + threadIdx.x) / kSplit;
+  const int k = (int)(threadIdx.x % kSplit);
+  const bool in = e < n;
+  const int nb = NB > 0 ? NB : nbins;
+  const double vs = in ? (double)vin[e] : 1.0;
+  const double x = in ? (double)xin[e] : 1.0;
+  double lk, lv, lx;
+  double lvv = __builtin_nan(""), lxx = __builtin_nan(""), lvx = __builtin_nan("");
+  const bool special = domain_special(vs, x, lk, lv, lx);
+  const double v = fabs(vs);
+  BinSums s{};
+  Bracket b{};
+  if (!special) {
+    b = find_bracket(v, x, margin_of<T>());
+    const int m_lo = (k * nb) / kSplit, m_hi = ((k + 1) * nb) / kSplit;
+    if constexpr (F64) {
+      const double ca = (double)b.tp;
+      s = sub_bins_f64<2>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.Gx, (double)b.t0, (double)b.t1, ca,
+                          coshm1_f64(ca));
+    } else {
+      s = sub_bins_f32<2>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.G, (double)b.t0, (double)b.t1);
+    }
+  }
+  s.S0 = group_sum(s.S0);
+  s.Sv = group_sum(s.Sv);
+  s.Sx = group_sum(s.Sx);
+  s.Svv = group_sum(s.Svv);
+  s.Sxx = group_sum(s.Sxx);
+  s.Svx = group_sum(s.Svx);
+  if constexpr (F64) {
+    s.Sv1 = group_sum(s.Sv1);
+    s.Sx1 = group_sum(s.Sx1);
+    s.Sq = group_sum(s.Sq);
+  }
+  if (!in || k != 0) return;
+  if (!special) hess_outputs<F64>(vs, v, b, s, nb, lk, lv, lx, lvv, lxx, lvx);
+  if (logk) logk[e] = (T)lk;
+  if (dv) dv[e] = (T)lv;
+  if (dx) dx[e] = (T)lx;
+  if (dvv) dvv[e] = (T)lvv;
+  if (dxx) dxx[e] = (T)lxx;
+  if (dvx) dvx[e] = (T)lvx;
 }
 
 template <typename T>
@@ -315,16 +383,18 @@ int grid_for(int64_t n, dim3& grid) {
 // Batches of at most this many elements run kSplit lanes per element.
 static std::atomic<int64_t> g_split_threshold{kDefaultSplitThreshold};
 
+int64_t split_threshold() { return g_split_threshold.load(std::memory_order_relaxed); }
+
 template <typename T, bool GRAD>
 static void launch_logk(dim3 grid, hipStream_t st, int64_t n, int nbins, const T* v, const T* x, const T* go, T* lk,
-                        T* dv, T* dx) {
-  if (n <= g_split_threshold.load(std::memory_order_relaxed)) {
+                        T* dv, T* dx, int* clear, bool force_split) {
+  if (force_split || n <= g_split_threshold.load(std::memory_order_relaxed)) {
     const dim3 sgrid((unsigned)((n * kSplit + kBlock - 1) / kBlock));
     switch (nbins) {
-      case 64: k_logk_split<T, 64, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
-      case 128: k_logk_split<T, 128, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
-      case 256: k_logk_split<T, 256, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
-      default: k_logk_split<T, 0, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx); break;
+      case 64: k_logk_split<T, 64, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx, clear); break;
+      case 128: k_logk_split<T, 128, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx, clear); break;
+      case 256: k_logk_split<T, 256, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx, clear); break;
+      default: k_logk_split<T, 0, GRAD><<<sgrid, kBlock, 0, st>>>(n, nbins, v, x, go, lk, dv, dx, clear); break;
     }
     return;
   }
@@ -337,24 +407,24 @@ static void launch_logk(dim3 grid, hipStream_t st, int64_t n, int nbins, const T
 }
 
 int logk_newton(int dtype, int64_t n, const void* v, const void* x, const void* go, void* lk, void* dv, void* dx,
-                int nbins, bool grad, hipStream_t st) {
+                int nbins, bool grad, hipStream_t st, int* clear, bool force_split) {
   dim3 grid;
   int rc = grid_for(n, grid);
   if (rc) return rc;
   if (dtype == BESSEL_F64) {
     if (grad)
       launch_logk<double, true>(grid, st, n, nbins, (const double*)v, (const double*)x, (const double*)go,
-                                (double*)lk, (double*)dv, (double*)dx);
+                                (double*)lk, (double*)dv, (double*)dx, clear, force_split);
     else
       launch_logk<double, false>(grid, st, n, nbins, (const double*)v, (const double*)x, nullptr, (double*)lk,
-                                 nullptr, nullptr);
+                                 nullptr, nullptr, clear, force_split);
   } else {
     if (grad)
       launch_logk<float, true>(grid, st, n, nbins, (const float*)v, (const float*)x, (const float*)go, (float*)lk,
-                               (float*)dv, (float*)dx);
+                               (float*)dv, (float*)dx, clear, force_split);
     else
       launch_logk<float, false>(grid, st, n, nbins, (const float*)v, (const float*)x, nullptr, (float*)lk, nullptr,
-                                nullptr);
+                                nullptr, clear, force_split);
   }
   return check_launch("k_logk");
 }
@@ -365,6 +435,16 @@ static void launch_hess(dim3 grid, hipStream_t st, int64_t n, int nbins, const v
   const T* xx = (const T*)x;
   T* p[6];
   for (int k = 0; k < 6; ++k) p[k] = (T*)o[k];
+  if (n <= g_split_threshold.load(std::memory_order_relaxed)) {
+    const dim3 sgrid((unsigned)((n * kSplit + kBlock - 1) / kBlock));
+    switch (nbins) {
+      case 64: k_logk_hess_split<T, 64><<<sgrid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+      case 128: k_logk_hess_split<T, 128><<<sgrid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+      case 256: k_logk_hess_split<T, 256><<<sgrid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+      default: k_logk_hess_split<T, 0><<<sgrid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
+    }
+    return;
+  }
   switch (nbins) {
     case 64: k_logk_hess<T, 64><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;
     case 128: k_logk_hess<T, 128><<<grid, kBlock, 0, st>>>(n, nbins, vv, xx, p[0], p[1], p[2], p[3], p[4], p[5]); break;

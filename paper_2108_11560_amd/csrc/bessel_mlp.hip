@@ -9,8 +9,14 @@
 // remains both the fallback and the reference for the predictor's error.
 //
 //   features  z = ((log max(|v|, 1e-3) - m_v) / s_v, (log x - m_x) / s_x)
-//   network   h1 = tanh(W1 z + b1), h2 = tanh(W2 h1 + b2), y = W3 h2 + b3
+//   network   h1 = clamp(W1 z + b1, -1, 1), h2 = phi(W2 h1 + b2), y = W3 h2 + b3
 //             (2 -> 64 -> 64 -> 2; FP32 master weights)
+//   activations  tanh-shaped, without transcendentals: the first layer's is
+//             the clamp to [-1, 1] (slope 1 inside, 0 outside), the second's
+//             phi(a) = u (3 - u^2) / 2 with u = clamp(a / 1.5, -1, 1), a cubic
+//             sigmoid (odd, slope 1 at 0, flat at +-1 from |a| = 1.5,
+//             continuously differentiable), phi'(a) = 1 - u^2; inference
+//             evaluates both in packed f16 arithmetic
 //   bracket   t0 = max(0, y0 - margin_t0) exp(y1), t1 = exp(y1 + margin_t1)
 //   targets   y0* = t0/t1, y1* = log t1 of the Newton bracket
 //   loss      mean of 1/2 (w0 e0^2 + w1 e1^2), e = y - y*, with weight alpha on
@@ -31,6 +37,7 @@
 #include "bessel.h"
 #include "bessel_device.hpp"
 #include "bessel_internal.hpp"
+#include "bessel_learned.hpp"
 
 namespace bk {
 
@@ -38,7 +45,6 @@ constexpr int kH = 64;
 constexpr int kNW = BESSEL_MLP_NWEIGHTS;  // 4482
 constexpr int kNP = BESSEL_MLP_NPARAMS;   // 4490
 constexpr int oW1 = 0, ob1 = 128, oW2 = 192, ob2 = 4288, oW3 = 4352, ob3 = 4480, oMeta = 4482;
-constexpr float kVFloor = 1e-3f;
 constexpr float kMarginF32 = 15.9423851528787422f;  // -log 2^-23
 
 // ---------------------------------------------------------------------------
@@ -51,7 +57,24 @@ __device__ __forceinline__ void mlp_features(const float* __restrict__ P, float 
   z1 = (lx - P[oMeta + 2]) / P[oMeta + 3];
 }
 
-constexpr float k2Log2e = 2.88539008178f;  // 2 log2(e)
+// The activation: phi(a) = u (3 - u^2) / 2, u = clamp(a / kActC, -1, 1), and
+// its derivative (3 / (2 kActC)) (1 - u^2), which is 1 - u^2 at kActC = 1.5.
+constexpr float kActC = 1.5f;
+__device__ __forceinline__ float act_phi(float a, float& dphi) {
+  const float u = fminf(fmaxf(a * (1.0f / kActC), -1.0f), 1.0f);
+  const float u2 = u * u;
+  dphi = (1.5f / kActC) * (1.0f - u2);
+  return 0.5f * u * (3.0f - u2);
+}
+__device__ __forceinline__ float act_phi(float a) {
+  float d;
+  return act_phi(a, d);
+}
+// The first layer's activation: clamp(a, -1, 1), derivative 1 inside.
+__device__ __forceinline__ float act_clamp(float a, float& d) {
+  d = fabsf(a) < 1.0f ? 1.0f : 0.0f;
+  return fminf(fmaxf(a, -1.0f), 1.0f);
+}
 
 // splitmix64 (Steele, Lea, Flood 2014): counter-based draws for minibatches.
 __device__ __forceinline__ uint64_t splitmix64(uint64_t z) {
@@ -98,6 +121,7 @@ typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 struct TrainLds {
   float h1[kTB][kH + 1];  // layer-1 activations
+  float g1[kTB][kH + 1];  // the derivatives of their activation
   float d2[kTB][kH + 1];  // layer-2 deltas
   float c[kTB][kH + 1];   // layer-2 activations, then layer-1 deltas
   float z[kTB][2];
@@ -135,7 +159,9 @@ __global__ __launch_bounds__(kTT) void k_mlp_grad(const float* __restrict__ P, i
 #pragma unroll
     for (int jj = 0; jj < 16; ++jj) {
       const int j = 16 * w + jj;
-      S.h1[l][j] = valid ? tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j]))) : 0.0f;
+      float d = 0.0f;
+      S.h1[l][j] = valid ? act_clamp(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])), d) : 0.0f;
+      S.g1[l][j] = d;
     }
     if (w == 0) {
       float y0t = 0.0f, y1t = 0.0f;
@@ -168,16 +194,17 @@ __global__ __launch_bounds__(kTT) void k_mlp_grad(const float* __restrict__ P, i
 #pragma unroll
     for (int st = 0; st < 4; ++st) acc[st] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b[st], acc[st], 0, 0, 0);
   }
-  // h2 = tanh(A2) and the tile's share of y = W3 h2 + b3: each lane holds 4
+  // h2 = phi(A2) and the tile's share of y = W3 h2 + b3: each lane holds 4
   // units of each of its 4 samples; the 4 lanes of a sample (l % 16 equal)
   // add up, then the shares of the tiles meet in LDS
   float y0p[4] = {0.0f, 0.0f, 0.0f, 0.0f}, y1p[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  float g2[4][4];  // phi'(a2)
 #pragma unroll
   for (int st = 0; st < 4; ++st)
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * w + 4 * lg + r;
-      const float h = tanhf(acc[st][r]);
+      const float h = act_phi(acc[st][r], g2[st][r]);
       acc[st][r] = h;
       y0p[st] = fmaf(P[oW3 + i], h, y0p[st]);
       y1p[st] = fmaf(P[oW3 + kH + i], h, y1p[st]);
@@ -226,9 +253,8 @@ __global__ __launch_bounds__(kTT) void k_mlp_grad(const float* __restrict__ P, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int i = 16 * w + 4 * lg + r, q = 16 * st + lr;
-      const float h = acc[st][r];
-      S.c[q][i] = h;
-      S.d2[q][i] = fmaf(P[oW3 + i], dy0[st], P[oW3 + kH + i] * dy1[st]) * (1.0f - h * h);
+      S.c[q][i] = acc[st][r];
+      S.d2[q][i] = fmaf(P[oW3 + i], dy0[st], P[oW3 + kH + i] * dy1[st]) * g2[st][r];
     }
   __syncthreads();
 
@@ -288,8 +314,7 @@ __global__ __launch_bounds__(kTT) void k_mlp_grad(const float* __restrict__ P, i
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       const int j = 16 * w + 4 * lg + r, q = 16 * st + lr;
-      const float h = S.h1[q][j];
-      S.c[q][j] = acc1[st][r] * (1.0f - h * h);
+      S.c[q][j] = acc1[st][r] * S.g1[q][j];
     }
   __syncthreads();  // the layer-1 deltas in S.c
   if (t < oW2) {
@@ -380,7 +405,8 @@ __global__ __launch_bounds__(kBlock) void k_mlp_reduce_adam(const float* __restr
 // Inference
 // ---------------------------------------------------------------------------
 
-// FP32 reference forward, one element per lane, exact tanh (for parity tests).
+// FP32 reference forward, one element per lane, the activation in FP32 (for
+// parity tests).
 __global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restrict__ P, int64_t n,
                                                             const float* __restrict__ v, const float* __restrict__ x,
                                                             float* __restrict__ y) {
@@ -389,12 +415,15 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restr
   float z0, z1;
   mlp_features(P, v[i], x[i], z0, z1);
   float h1[kH];
-  for (int j = 0; j < kH; ++j) h1[j] = tanhf(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])));
+  for (int j = 0; j < kH; ++j) {
+    float d;
+    h1[j] = act_clamp(fmaf(P[oW1 + 2 * j], z0, fmaf(P[oW1 + 2 * j + 1], z1, P[ob1 + j])), d);
+  }
   float y0 = P[ob3], y1 = P[ob3 + 1];
   for (int k = 0; k < kH; ++k) {
     float a = P[ob2 + k];
     for (int j = 0; j < kH; ++j) a = fmaf(P[oW2 + k * kH + j], h1[j], a);
-    const float h2 = tanhf(a);
+    const float h2 = act_phi(a);
     y0 = fmaf(P[oW3 + k], h2, y0);
     y1 = fmaf(P[oW3 + kH + k], h2, y1);
   }
@@ -402,27 +431,34 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_f32(const float* __restr
   y[2 * i + 1] = y1;
 }
 
-typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 
 // Inference operands, rebuilt from the FP32 parameters whenever they change
-// (k_mlp_pack) so that a wavefront loads its fragments with a few 16-byte loads:
+// (k_mlp_pack) so that a wavefront loads its fragments with a few 16-byte loads.
+// Each layer's MFMA produces A = k a + 1/2 for its pre-activation a, with
+// k = 1/2 (first layer) or 1 / (2 kActC) (second), so that w = clamp(A, 0, 1)
+// is the conversion to f16 with its clamp, and the activations are
+//   clamp(a, -1, 1) = 2 w - 1,   phi(a) = 2 S(w) - 1,  S(w) = w^2 (3 - 2 w);
+// the next layer takes w or S through  W (2 X - 1) + b = 2 W X + (b - sum W).
 //   header  z0 = log2 max(|v|, 1e-3) * c_v + d_v,  z1 = log2 x * c_x + d_x
 //           (c = ln 2 / s, d = -m / s), e^{margin_t1}, margin_t0, b3'[2]
-//   A1      layer-1 fragments: for hidden tile ht and row lr, the eight bf16
+//   A1      layer-1 fragments: for hidden tile ht and row lr, the eight f16
 //           values (Wh0, Wh0, Wl0, Wh1, Wh1, Wl1, bh, bl) -- hi/lo splits of
-//           2 log2(e) (W1, b1) -- which meet (zh0, zl0, zh0, zh1, zl1, zh1, 1, 1)
-//   A2      layer-2 fragments (bf16 of -2 * 2 log2(e) W2) per output tile,
-//           k-block and lane, columns in the order the layer-1 results reach
-//           the lane
-//   B2      2 log2(e) (b2 + sum_j W2[., j]) in accumulator order
-//   A3      layer-3 fragments (bf16 of -2 W3) per element tile et and
-//           k-block: output c on row 4 et + c, zero rows elsewhere, so that
-//           the four tiles share one accumulator and each lane ends with the
-//           outputs of its own element;  b3' = b3 + sum_i W3[., i]
-// With s = 1 / (1 + 2^{a'}), a' = 2 log2(e) a, tanh(a) = 1 - 2 s, so each layer
-// takes the s of the one before:  W h + b = (b + sum W) - 2 W s.
-constexpr int qHdr = 0, qA1 = 16, qA2 = qA1 + 4 * 16 * 4, qB2 = qA2 + 4 * 2 * 64 * 4, qA3 = qB2 + kH,
+//           W1 / 2 and b1 / 2 + 1/2 -- which meet
+//           (zh0, zl0, zh0, zh1, zl1, zh1, 1, 1)
+//   A2      layer-2 fragments (f16 of W2 / kActC) per output tile, k-block and
+//           lane, columns in the order the layer-1 results reach the lane
+//   B2      (b2 - sum_j W2[., j]) / (2 kActC) + 1/2 in accumulator order
+//   A3      layer-3 fragments (f16 of 2 W3) per element tile et and k-block:
+//           output c on row 4 et + c, zero rows elsewhere, so that the four
+//           tiles share one accumulator and each lane ends with the outputs of
+//           its own element;  b3' = b3 - sum_i W3[., i]
+constexpr int qA1 = 16, qA2 = qA1 + 4 * 16 * 4, qB2 = qA2 + 4 * 2 * 64 * 4, qA3 = qB2 + kH,
               kNQ = qA3 + 4 * 2 * 64 * 4;
+constexpr float kPreScale1 = 0.5f;          // layer 1: A = a / 2 + 1/2
+constexpr float kPreScale = 0.5f / kActC;  // layer 2: A = a / (2 kActC) + 1/2
 
 // hidden unit fed by k-slot j of lane group g in k-block kb of layer 2: the
 // layer-1 accumulators of tiles 2kb and 2kb+1 hold rows 4g..4g+3 of each
@@ -430,34 +466,35 @@ __host__ __device__ constexpr int l2_col(int kb, int g, int j) { return 32 * kb 
 
 __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ P, float* __restrict__ Q) {
   const int t = threadIdx.x;
-  __bf16* a1 = reinterpret_cast<__bf16*>(Q + qA1);
-  __bf16* a2 = reinterpret_cast<__bf16*>(Q + qA2);
+  _Float16* a1 = reinterpret_cast<_Float16*>(Q + qA1);
+  _Float16* a2 = reinterpret_cast<_Float16*>(Q + qA2);
   if (t < kH) {
     const int h = t;  // = 16 ht + lr
-    const float w[3] = {k2Log2e * P[oW1 + 2 * h], k2Log2e * P[oW1 + 2 * h + 1], k2Log2e * P[ob1 + h]};
-    __bf16 hi[3], lo[3];
+    const float w[3] = {kPreScale1 * P[oW1 + 2 * h], kPreScale1 * P[oW1 + 2 * h + 1],
+                        fmaf(kPreScale1, P[ob1 + h], 0.5f)};
+    _Float16 hi[3], lo[3];
     for (int k = 0; k < 3; ++k) {
-      hi[k] = (__bf16)w[k];
-      lo[k] = (__bf16)(w[k] - (float)hi[k]);
+      hi[k] = (_Float16)w[k];
+      lo[k] = (_Float16)(w[k] - (float)hi[k]);
     }
-    const __bf16 e[8] = {hi[0], hi[0], lo[0], hi[1], hi[1], lo[1], hi[2], lo[2]};
+    const _Float16 e[8] = {hi[0], hi[0], lo[0], hi[1], hi[1], lo[1], hi[2], lo[2]};
     for (int j = 0; j < 8; ++j) a1[h * 8 + j] = e[j];
     double rs = (double)P[ob2 + h];
-    for (int j = 0; j < kH; ++j) rs += (double)P[oW2 + h * kH + j];
-    Q[qB2 + h] = k2Log2e * (float)rs;  // 16 ho + 4 g + r is the natural order
+    for (int j = 0; j < kH; ++j) rs -= (double)P[oW2 + h * kH + j];
+    Q[qB2 + h] = (float)fma((double)kPreScale, rs, 0.5);  // 16 ho + 4 g + r is the natural order
   }
-  __bf16* a3 = reinterpret_cast<__bf16*>(Q + qA3);
+  _Float16* a3 = reinterpret_cast<_Float16*>(Q + qA3);
   for (int idx = t; idx < 4 * 2 * 64 * 8; idx += kBlock) {
     const int j = idx & 7, l = (idx >> 3) & 63, kb = (idx >> 9) & 1, hi = idx >> 10;
     const int row = 16 * hi + (l & 15);
-    a2[idx] = (__bf16)(-2.0f * k2Log2e * P[oW2 + row * kH + l2_col(kb, l >> 4, j)]);
+    a2[idx] = (_Float16)(2.0f * kPreScale * P[oW2 + row * kH + l2_col(kb, l >> 4, j)]);
     // layer 3 for element tile et = hi: output c on row 4 et + c
     const int c = (l & 15) - 4 * hi;
-    a3[idx] = (c == 0 || c == 1) ? (__bf16)(-2.0f * P[oW3 + c * kH + l2_col(kb, l >> 4, j)]) : (__bf16)0.0f;
+    a3[idx] = (c == 0 || c == 1) ? (_Float16)(2.0f * P[oW3 + c * kH + l2_col(kb, l >> 4, j)]) : (_Float16)0.0f;
   }
   if (t < 2) {
     double s = (double)P[ob3 + t];
-    for (int i = 0; i < kH; ++i) s += (double)P[oW3 + t * kH + i];
+    for (int i = 0; i < kH; ++i) s -= (double)P[oW3 + t * kH + i];
     Q[qHdr + 6 + t] = (float)s;
   }
   if (t == 0) {
@@ -471,19 +508,40 @@ __global__ __launch_bounds__(kBlock) void k_mlp_pack(const float* __restrict__ P
   }
 }
 
-__device__ __forceinline__ void mlp_features_q(const float* __restrict__ Q, float v, float x, float& z0, float& z1) {
-  z0 = fmaf(hlog2(fmaxf(fabsf(v), kVFloor)), Q[qHdr + 0], Q[qHdr + 1]);
-  z1 = fmaf(hlog2(x), Q[qHdr + 2], Q[qHdr + 3]);
+// clamp(A, 0, 1) for two accumulators as packed f16: the clamp rides on the
+// conversion (v_cvt_pk_f16_f32 with its clamp bit), one instruction.
+__device__ __forceinline__ f16x2 clamp_pair(float a, float b) {
+  const _Float16 zero = (_Float16)0.0f, one = (_Float16)1.0f;
+  const f16x2 w = (f16x2){(_Float16)a, (_Float16)b};
+  return __builtin_elementwise_min(__builtin_elementwise_max(w, (f16x2){zero, zero}), (f16x2){one, one});
+}
+
+// S(clamp(A, 0, 1)) for two accumulators: the conversion with its clamp, then
+// one packed FMA and two packed products; 4 instructions for 2 activations.
+__device__ __forceinline__ f16x2 cubic_pair(float a, float b) {
+  const _Float16 two = (_Float16)2.0f, three = (_Float16)3.0f;
+  const f16x2 w = clamp_pair(a, b);
+  return (w * w) * (w * (f16x2){-two, -two} + (f16x2){three, three});
+}
+
+// The activations of one 16 x 16 accumulator pair (rows 4g..4g+3 of two
+// tiles), packed as the next layer's f16x8 k-slots: w (CUBIC false) or S(w).
+template <bool CUBIC>
+__device__ __forceinline__ f16x8 act_tiles(f32x4 d0, f32x4 d1) {
+  auto pair = [](float a, float b) { return CUBIC ? cubic_pair(a, b) : clamp_pair(a, b); };
+  const f16x4 p = __builtin_shufflevector(pair(d0[0], d0[1]), pair(d0[2], d0[3]), 0, 1, 2, 3);
+  const f16x4 q = __builtin_shufflevector(pair(d1[0], d1[1]), pair(d1[2], d1[3]), 0, 1, 2, 3);
+  return __builtin_shufflevector(p, q, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
 // One wavefront evaluates the network for its 64 elements (lane = element),
-// every layer on v_mfma_f32_16x16x32_bf16 or the VALU:
+// every layer on v_mfma_f32_16x16x32_f16 or the VALU:
 //   A (16 x 32):  lane l holds row l%16, k-slots 8(l/16)..8(l/16)+7
 //   B (32 x 16):  lane l holds column l%16, k-slots 8(l/16)..8(l/16)+7
 //   D (16 x 16):  lane l holds column l%16, rows 4(l/16)..4(l/16)+3
 // Layer 1: D[hidden][element] = A1 * Z, where element tile et takes the
 // features only from lane group et (its own elements), zeros elsewhere.
-// Layer 2: D[hidden out][element] = A2 * S1^T + B2; the layer-1 accumulators
+// Layer 2: D[hidden out][element] = A2 * W1^T + B2; the layer-1 activations
 // of a lane are already its B fragments (k-slots permuted as l2_col).
 // Layer 3: D[4 et + c][element] += A3(et) * S2^T over the four element tiles
 // into one accumulator; lane l = 16 g + e ends with rows 4g, 4g + 1 of column
@@ -492,11 +550,11 @@ __device__ __forceinline__ void mlp_features_q(const float* __restrict__ Q, floa
 __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float z0, float z1, float& y0, float& y1) {
   const int l = threadIdx.x & 63;
   const int lr = l & 15, lg = l >> 4;
-  bf16x8 zf;
+  f16x8 zf;
   {
-    const __bf16 z0h = (__bf16)z0, z1h = (__bf16)z1;
-    const __bf16 z0l = (__bf16)(z0 - (float)z0h), z1l = (__bf16)(z1 - (float)z1h);
-    const __bf16 one = (__bf16)1.0f;
+    const _Float16 z0h = (_Float16)z0, z1h = (_Float16)z1;
+    const _Float16 z0l = (_Float16)(z0 - (float)z0h), z1l = (_Float16)(z1 - (float)z1h);
+    const _Float16 one = (_Float16)1.0f;
     zf[0] = z0h;
     zf[1] = z0l;
     zf[2] = z0h;
@@ -506,12 +564,12 @@ __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float
     zf[6] = one;
     zf[7] = one;
   }
-  bf16x8 zero;
+  f16x8 zero;
 #pragma unroll
-  for (int j = 0; j < 8; ++j) zero[j] = (__bf16)0.0f;
-  const bf16x8* A1 = reinterpret_cast<const bf16x8*>(Q + qA1);
-  const bf16x8* A2 = reinterpret_cast<const bf16x8*>(Q + qA2);
-  bf16x8 a1[4], a2[4][2], a3[4][2];
+  for (int j = 0; j < 8; ++j) zero[j] = (_Float16)0.0f;
+  const f16x8* A1 = reinterpret_cast<const f16x8*>(Q + qA1);
+  const f16x8* A2 = reinterpret_cast<const f16x8*>(Q + qA2);
+  f16x8 a1[4], a2[4][2], a3[4][2];
   f32x4 b2[4];
 #pragma unroll
   for (int ht = 0; ht < 4; ++ht) a1[ht] = A1[ht * 16 + lr];
@@ -520,32 +578,30 @@ __device__ __forceinline__ void mlp_wave_mfma(const float* __restrict__ Q, float
     a2[ho][0] = A2[(ho * 2 + 0) * 64 + l];
     a2[ho][1] = A2[(ho * 2 + 1) * 64 + l];
     b2[ho] = *reinterpret_cast<const f32x4*>(Q + qB2 + 16 * ho + 4 * lg);
-    const bf16x8* A3 = reinterpret_cast<const bf16x8*>(Q + qA3);
+    const f16x8* A3 = reinterpret_cast<const f16x8*>(Q + qA3);
     a3[ho][0] = A3[(ho * 2 + 0) * 64 + l];  // ho doubles as the element tile here
     a3[ho][1] = A3[(ho * 2 + 1) * 64 + l];
   }
   f32x4 acc = {Q[qHdr + 6], Q[qHdr + 7], 0.0f, 0.0f};  // rows 4g + c start at b3'[c]
 #pragma unroll
   for (int et = 0; et < 4; ++et) {
-    const bf16x8 bz = (lg == et) ? zf : zero;
-    bf16x8 h[2];
+    const f16x8 bz = (lg == et) ? zf : zero;
+    f32x4 d1[4];
 #pragma unroll
     for (int ht = 0; ht < 4; ++ht) {
-      f32x4 d = {0.0f, 0.0f, 0.0f, 0.0f};
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1[ht], bz, d, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h[ht >> 1][4 * (ht & 1) + r] = (__bf16)hrcp(1.0f + hexp2(d[r]));
+      d1[ht] = (f32x4){0.0f, 0.0f, 0.0f, 0.0f};
+      d1[ht] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a1[ht], bz, d1[ht], 0, 0, 0);
     }
-    bf16x8 h3[2];
+    const f16x8 h[2] = {act_tiles<false>(d1[0], d1[1]), act_tiles<false>(d1[2], d1[3])};
+    f32x4 d2[4];
 #pragma unroll
     for (int ho = 0; ho < 4; ++ho) {
-      f32x4 d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][0], h[0], b2[ho], 0, 0, 0);
-      d = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a2[ho][1], h[1], d, 0, 0, 0);
-#pragma unroll
-      for (int r = 0; r < 4; ++r) h3[ho >> 1][4 * (ho & 1) + r] = (__bf16)hrcp(1.0f + hexp2(d[r]));
+      d2[ho] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[ho][0], h[0], b2[ho], 0, 0, 0);
+      d2[ho] = __builtin_amdgcn_mfma_f32_16x16x32_f16(a2[ho][1], h[1], d2[ho], 0, 0, 0);
     }
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[et][0], h3[0], acc, 0, 0, 0);
-    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a3[et][1], h3[1], acc, 0, 0, 0);
+    const f16x8 h3[2] = {act_tiles<true>(d2[0], d2[1]), act_tiles<true>(d2[2], d2[3])};
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3[et][0], h3[0], acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_f16(a3[et][1], h3[1], acc, 0, 0, 0);
   }
   y0 = acc[0];
   y1 = acc[1];
@@ -567,17 +623,13 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_mfma(const float* __rest
 
 // Tabulated network (range mode BESSEL_RANGE_MLP_TABLE).  The features are
 // two-dimensional, so the network's outputs can be tabulated once per change
-// of the parameters: k_mlp_tab_nodes runs the bf16-MFMA inference above on a
+// of the parameters: k_mlp_tab_nodes runs the f16-MFMA inference above on a
 // kTab x kTab grid of the feature plane, z in [-kTabZ, kTabZ]^2, and
 // k_mlp_tab_cells stores per cell the bilinear coefficients of both outputs
 // (value, d/du, d/dw, d2/dudw; 8 floats = one aligned 32-byte record).  An
 // element then costs one record load and six FMAs instead of 128 activations.
 // Interpolation moves the outputs by ~1e-3 (y0) and ~4e-4 (y1) on the scale
 // workload, far inside the margins; the check after the bins still decides.
-constexpr int kTab = 256;
-constexpr float kTabZ = 4.0f;
-constexpr int kCells = kTab - 1;
-
 // grid: kTab * kTab / kBlock blocks (every lane a node; the whole wavefront
 // takes part in the MFMAs)
 __global__ __launch_bounds__(kBlock) void k_mlp_tab_nodes(const float* __restrict__ Q, float* __restrict__ nodes) {
@@ -602,21 +654,6 @@ __global__ __launch_bounds__(kBlock) void k_mlp_tab_cells(const float* __restric
   cells[2 * c + 1] = make_float4(a[1], d[1] - a[1], b[1] - a[1], (e[1] - d[1]) - (b[1] - a[1]));
 }
 
-// Bilinear lookup; features outside the table are clamped to its edge (their
-// brackets are then usually rejected by the check and recomputed).
-__device__ __forceinline__ void mlp_table(const float4* __restrict__ cells, float z0, float z1, float& y0,
-                                          float& y1) {
-  const float s = (float)(kTab - 1) / (2.0f * kTabZ);
-  const float u = fminf(fmaxf((z0 + kTabZ) * s, 0.0f), (float)kCells - 1e-3f);
-  const float w = fminf(fmaxf((z1 + kTabZ) * s, 0.0f), (float)kCells - 1e-3f);
-  const int i = (int)u, j = (int)w;
-  const float fu = u - (float)i, fw = w - (float)j;
-  const float4 r0 = cells[2 * (i * kCells + j)];
-  const float4 r1 = cells[2 * (i * kCells + j) + 1];
-  y0 = fmaf(fw, fmaf(fu, r0.w, r0.z), fmaf(fu, r0.y, r0.x));
-  y1 = fmaf(fw, fmaf(fu, r1.w, r1.z), fmaf(fu, r1.y, r1.x));
-}
-
 __global__ __launch_bounds__(kBlock) void k_mlp_forward_table(const float* __restrict__ Q,
                                                               const float4* __restrict__ cells, int64_t n,
                                                               const float* __restrict__ v,
@@ -630,28 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_forward_table(const float* __res
   y[2 * i + 1] = y1;
 }
 
-// g at one point for the shift of a learned bracket, FP32 hardware form.  Any finite shift is exact (log K = G + log(h S0) with S0 relative to
-// the same G); inside the bracket g >= max g - L, so the exponents stay below
-// L and FP32 cannot overflow.
-__device__ __forceinline__ float shift_at(float v, float x, float t) {
-  const float e = hexp2(kLog2eF * t);
-  return log_cosh_f32(v * t) - 0.5f * x * (e + hrcp(e));
-}
-
-// Acceptance of a learned bracket after its bins (all relative to e^{G}):
-//   coverage   the end terms are at most eps_32 (t0 = 0 needs no lower test);
-//              since G <= max g, this bounds g at the ends by max g + log eps;
-//   resolution the even-node and odd-node rules (step 2h) agree to 1e-5, so
-//              the full rule's error is far below FP32 resolution;
-//   finiteness of every sum.
-__device__ __forceinline__ bool accept_bins(const BinSums& s, float t0) {
-  const float tau = 1.1920929e-07f;
-  const bool cover = (t0 == 0.0f || s.term0 <= tau) && s.termN <= tau;
-  const bool resolved = fabs(s.Seven - s.Sodd) <= 1e-5 * 0.5 * (s.Seven + s.Sodd);
-  return cover && resolved && isfinite(s.S0) && s.S0 > 0.0;
-}
-
-// Fused: network (bf16 MFMA, or its table with TAB) -> bracket -> checked FP32
+// Fused: network (f16 MFMA, or its table with TAB) -> bracket -> checked FP32
 // bins -> outputs, or the element index onto the worklist (count at work[0],
 // indices from work[1]).
 template <bool GRAD, int NB, bool TAB>
@@ -677,44 +693,38 @@ __global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q
   if constexpr (TAB) mlp_table(cells, z0, z1, y0, y1);
   else mlp_wave_mfma(Q, z0, z1, y0, y1);
   bool ok = true;
-  float t0 = 0.0f, t1 = 0.0f, G = 0.0f;
+  LearnedBracket lb{};
   if (in && !special) {
     const float v = fabsf(vs);
-    const float t1r = hexp2(kLog2eF * y1);  // predicted t1 before widening
-    t0 = fmaxf(0.0f, y0 - Q[qHdr + 5]) * t1r;
-    t1 = t1r * Q[qHdr + 4];
-    // shift: the largest of g at the midpoint, at asinh(v/x) (the peak when
-    // v t_p >> 1, clamped into the bracket) and, for t0 = 0, g(0) = -x
-    const float r = fminf(v * hrcp(xf), 1e18f);
-    const float ta = fminf(fmaxf(kLn2F * hlog2(r + hsqrt(fmaf(r, r, 1.0f))), t0), t1);
-    G = fmaxf(shift_at(v, xf, 0.5f * (t0 + t1)), shift_at(v, xf, ta));
-    if (t0 == 0.0f) G = fmaxf(G, -xf);
-    ok = isfinite(t1) && t1 > t0 && isfinite(G);
+    BinSums s;
+    ok = learned_bins<GRAD ? 1 : 0>(Q, (double)v, (double)xf, y0, y1, nb, lb, s);
     if (ok) {
-      const BinSums s = bins_f32<GRAD, true>(nb, (double)v, (double)xf, (double)G, (double)t0, (double)t1);
-      ok = accept_bins(s, t0);
-      if (ok) {
-        const double h = ((double)t1 - (double)t0) / (double)nb;
-        const double rS0 = rcp_of<false>(s.S0);
-        lk = (double)G + log_of<false>(h * s.S0);
-        if (GRAD) {
-          dvv = (v == 0.0f) ? 0.0 : copysign(s.Sv * rS0, (double)vs);
-          dxv = -s.Sx * rS0;
-        }
+      const double h = ((double)lb.t1 - (double)lb.t0) / (double)nb;
+      const double rS0 = rcp_of<false>(s.S0);
+      lk = (double)lb.G + log_of<false>(h * s.S0);
+      if (GRAD) {
+        dvv = (v == 0.0f) ? 0.0 : copysign(s.Sv * rS0, (double)vs);
+        dxv = -s.Sx * rS0;
       }
     }
   }
-  // compaction of the failures: one atomic per wavefront
+  // compaction of the failures: the block's wavefronts count theirs in LDS
+  // and one atomic per block (not per wavefront: a single global counter
+  // serialises its atomics, which costs as much as the kernel itself when a
+  // few percent of the elements fail) reserves the block's stretch of the list
+  __shared__ int s_count, s_base;
   const bool fail = in && !special && !ok;
   const unsigned long long mask = __ballot(fail);
-  if (mask) {
-    const int lane = threadIdx.x & 63;
-    const int leader = __ffsll((long long)mask) - 1;
-    int base = 0;
-    if (lane == leader) base = atomicAdd(work, __popcll(mask));
-    base = __shfl(base, leader);
-    if (fail) work[1 + base + __popcll(mask & ((1ULL << lane) - 1ULL))] = (int)i;
-  }
+  const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) s_count = 0;
+  __syncthreads();
+  int woff = 0;
+  if (lane == 0 && mask) woff = atomicAdd(&s_count, __popcll(mask));
+  woff = __shfl(woff, 0);
+  __syncthreads();
+  if (threadIdx.x == 0 && s_count > 0) s_base = atomicAdd(work, s_count);
+  __syncthreads();
+  if (fail) work[1 + s_base + woff + __popcll(mask & ((1ULL << lane) - 1ULL))] = (int)i;
   if (!in) return;
   if (fb) fb[i] = fail ? 1 : 0;
   if (fail) return;
@@ -729,10 +739,10 @@ __global__ __launch_bounds__(kBlock) void k_logk_mlp(const float* __restrict__ Q
     dx[i] = (float)dxv;
   }
   if (t0o) {
-    t0o[i] = special ? __builtin_nanf("") : t0;
-    t1o[i] = special ? __builtin_nanf("") : t1;
-    if (tpo) tpo[i] = special ? __builtin_nanf("") : 0.5f * (t0 + t1);
-    if (gpo) gpo[i] = special ? __builtin_nanf("") : G;
+    t0o[i] = special ? __builtin_nanf("") : lb.t0;
+    t1o[i] = special ? __builtin_nanf("") : lb.t1;
+    if (tpo) tpo[i] = special ? __builtin_nanf("") : lb.tg;
+    if (gpo) gpo[i] = special ? __builtin_nanf("") : lb.G;
   }
 }
 
@@ -847,6 +857,15 @@ extern "C" int bessel_mlp_create(const float* params, int64_t nparams, bessel_ml
   if (e == hipSuccess) e = hipMalloc((void**)&m->adam_m, kNW * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&m->adam_s, kNW * sizeof(float));
   if (e == hipSuccess) e = hipMalloc((void**)&m->grad, (kNW + 1) * sizeof(float));
+  // the network's table (2.6 MB) is allocated here, so that building it later
+  // (on the first call in the table mode after a parameter change) allocates
+  // nothing
+  if (e == hipSuccess) e = hipMalloc((void**)&m->tab_nodes, (size_t)2 * kTab * kTab * sizeof(float));
+  if (e == hipSuccess) e = hipMalloc((void**)&m->tab_cells, (size_t)2 * kCells * kCells * sizeof(float4));
+  if (e == hipSuccess) {
+    m->cap_tab_nodes = (int64_t)2 * kTab * kTab;
+    m->cap_tab_cells = (int64_t)2 * kCells * kCells;
+  }
   if (e == hipSuccess) e = hipMemset(m->adam_m, 0, kNW * sizeof(float));
   if (e == hipSuccess) e = hipMemset(m->adam_s, 0, kNW * sizeof(float));
   if (e == hipSuccess) {
@@ -872,10 +891,10 @@ extern "C" int bessel_mlp_create(const float* params, int64_t nparams, bessel_ml
 extern "C" int bessel_mlp_destroy(bessel_mlp* m) {
   if (!m) return BESSEL_OK;
   (void)hipDeviceSynchronize();
-  void* sync_ptrs[] = {m->params, m->packed, m->adam_m, m->adam_s, m->grad};
+  void* sync_ptrs[] = {m->params, m->packed, m->adam_m, m->adam_s, m->grad, m->tab_nodes, m->tab_cells};
   for (void* p : sync_ptrs)
     if (p) (void)hipFree(p);
-  void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work, m->tab_nodes, m->tab_cells};  // hipMallocAsync
+  void* async_ptrs[] = {m->partial, m->labels, m->losses, m->work};  // hipMallocAsync
   for (void* p : async_ptrs)
     if (p) (void)hipFreeAsync(p, nullptr);
   (void)hipDeviceSynchronize();
@@ -1015,9 +1034,7 @@ static int refresh_table(const bessel_mlp* mc, hipStream_t st) {
   bessel_mlp* m = const_cast<bessel_mlp*>(mc);
   int rc = refresh_packed(m, st);
   if (rc || !m->table_stale) return rc;
-  rc = ensure(m->tab_nodes, m->cap_tab_nodes, (int64_t)2 * kTab * kTab, st, "network table");
-  if (rc == BESSEL_OK) rc = ensure(m->tab_cells, m->cap_tab_cells, (int64_t)2 * kCells * kCells, st, "network table");
-  if (rc) return rc;
+  if (!m->tab_nodes || !m->tab_cells) return set_error(BESSEL_ERR_ARG, "the handle has no table buffers");
   static_assert((kTab * kTab) % kBlock == 0, "the node grid fills whole blocks");
   k_mlp_tab_nodes<<<kTab * kTab / kBlock, kBlock, 0, st>>>(m->packed, m->tab_nodes);
   rc = check_launch("k_mlp_tab_nodes");
@@ -1028,10 +1045,22 @@ static int refresh_table(const bessel_mlp* mc, hipStream_t st) {
   return rc;
 }
 
+namespace bk {
+
+int mlp_table_operands(const bessel_mlp* m, hipStream_t st, const float** Q, const float4** cells) {
+  const int rc = refresh_table(m, st);
+  if (rc) return rc;
+  *Q = m->packed;
+  *cells = m->tab_cells;
+  return BESSEL_OK;
+}
+
+}  // namespace bk
+
 extern "C" int bessel_mlp_forward(const bessel_mlp* m, int64_t n, const float* v, const float* x, float* y, int mode,
                                   void* hip_stream) {
   if (!m || (n > 0 && (!v || !x || !y))) return set_error(BESSEL_ERR_ARG, "NULL argument");
-  if (mode < 0 || mode > 2) return set_error(BESSEL_ERR_ARG, "mode must be 0 (FP32), 1 (bf16 MFMA) or 2 (table)");
+  if (mode < 0 || mode > 2) return set_error(BESSEL_ERR_ARG, "mode must be 0 (FP32), 1 (f16 MFMA) or 2 (table)");
   if (n == 0) return BESSEL_OK;
   dim3 grid;
   int rc = grid_for(n, grid);
@@ -1121,6 +1150,12 @@ static int run_mlp(int64_t n, const float* v, const float* x, const float* go, f
 
 int logk_mlp(int64_t n, const float* v, const float* x, const float* go, float* lk, float* dv, float* dx, int nbins,
              bool grad, const bessel_mlp* mlp, bool table, hipStream_t st) {
+  // Small batches (at most the split threshold) run the Newton bracket on the
+  // 16-lanes-per-element layout, one launch: there one lane per element
+  // leaves most of the chip idle, and the predictor saves nothing; the
+  // handle's fallback count reads 0 afterwards.
+  if (n <= split_threshold())
+    return logk_newton(BESSEL_F32, n, v, x, go, lk, dv, dx, nbins, grad, st, mlp->work, true);
   if (grad)
     return run_mlp<true>(n, v, x, go, lk, dv, dx, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp, table, st);
   return run_mlp<false>(n, v, x, nullptr, lk, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nbins, mlp,

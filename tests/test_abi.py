@@ -115,8 +115,9 @@ def test_error_status_names():
 
 def test_gh_argument_errors(lib):
     args = [FAKE_A, FAKE_A, FAKE_A, FAKE_A, 4, FAKE_B, NULL, FAKE_C, NULL, NULL, NULL, NULL]
-    assert lib.bessel_gh_logk_sum(4, *args, 128, 1, NULL, NULL) == -7  # learned range: unsupported here
-    assert lib.bessel_gh_logk_sum(4, *args, 128, 2, NULL, NULL) == -7
+    assert lib.bessel_gh_logk_sum(4, *args, 128, 1, NULL, NULL) == -7  # per-element network: not here
+    assert lib.bessel_gh_logk_sum(4, *args, 128, 2, NULL, NULL) == -4  # the table needs a predictor
+    assert lib.bessel_gh_logk_sum(4, *args, 128, 3, NULL, NULL) == -4
     assert lib.bessel_gh_logk_sum(4, *args, 1, 0, NULL, NULL) == -3
     assert lib.bessel_gh_logk_sum(-1, *args, 128, 0, NULL, NULL) == -1
     assert lib.bessel_gh_logk_sum(0, *args, 128, 0, NULL, NULL) == 0
@@ -124,7 +125,8 @@ def test_gh_argument_errors(lib):
     assert lib.bessel_gh_logk_sum(4, *bad, 128, 0, NULL, NULL) == -6
     # the allocation-free variant runs the same checks first
     for fn in (lib.bessel_gh_logk_sum, lib.bessel_gh_logk_sum_noalloc):
-        assert fn(4, *args, 128, 2, NULL, NULL) == -7
+        assert fn(4, *args, 128, 1, NULL, NULL) == -7
+        assert fn(4, *args, 128, 2, NULL, NULL) == -4
         assert fn(4, *args, 1, 0, NULL, NULL) == -3
         assert fn(4, *bad, 128, 0, NULL, NULL) == -6
         assert fn(0, *args, 128, 0, NULL, NULL) == 0

@@ -88,7 +88,7 @@ def test_learned_2p24(bk):
     mlp.train(dev(vtr, torch.float32), dev(xtr, torch.float32), steps=20000, batch=8192, lr=3e-3, lr_final=3e-5,
               seed=1)
     vca, xca, _ = workloads.scale_pairs(1 << 16, seed=8)
-    M.calibrate_margins(mlp, dev(vca, torch.float32), dev(xca, torch.float32), target_fallback=0.005)
+    M.calibrate_margins(mlp, dev(vca, torch.float32), dev(xca, torch.float32), target_fallback=0.001)
     v, x, _ = workloads.scale_pairs(1 << 24, seed=1)
     v32, x32 = dev(v, torch.float32), dev(x, torch.float32)
     ref = bk.logk(v32.double(), x32.double())

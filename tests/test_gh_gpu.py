@@ -116,3 +116,83 @@ def test_ragged_and_empty(bk):
         check_against_reference(got, lam, alpha, delta, mu, y[:ns], None)
     empty = bk.gh_logk_sum(dev32(lam), dev32(alpha), dev32(delta), dev32(mu), dev32(np.zeros(0)))
     assert np.all(host(empty[0]) == 0.0)
+
+
+# ---- the bracket from the network's table (range="mlp_table") --------------
+
+
+@pytest.fixture(scope="module")
+def net(bk):
+    """A predictor trained and calibrated as the benchmark's (2^20 scale pairs,
+    20 000 Adam steps, margins on 2^16 held-out pairs)."""
+    from paper_2108_11560_amd import mlp as M
+    m = M.RangeMLP(M.glorot_params(0))
+    v, x, _ = workloads.scale_pairs(1 << 20, seed=4)
+    m.train(dev32(v), dev32(x), steps=20000, batch=8192, lr=3e-3, lr_final=3e-5, seed=1)
+    vc, xc, _ = workloads.scale_pairs(1 << 16, seed=8)
+    M.calibrate_margins(m, dev32(vc), dev32(xc), range="mlp_table")
+    yield m
+    m.close()
+
+
+def test_table_range_all_sets_256_samples(bk, net):
+    lam, alpha, delta, mu, y, gs = workloads.gh_batch(1024, 65536, seed=5, grad_seed=15)
+    lam, alpha, delta, mu, y, gs = (f32(a) for a in (lam, alpha, delta, mu, y, gs))
+    y = y[:256]
+    got = bk.gh_logk_sum(dev32(lam), dev32(alpha), dev32(delta), dev32(mu), dev32(y), grad_sum=dev32(gs),
+                         range="mlp_table", mlp=net)
+    check_against_reference(got, lam, alpha, delta, mu, y, gs)
+
+
+def test_table_range_full_sets_at_scale(bk, net):
+    lam, alpha, delta, mu, y, gs = workloads.gh_batch(1024, 65536, seed=5, grad_seed=15)
+    lam, alpha, delta, mu, y, gs = (f32(a) for a in (lam, alpha, delta, mu, y, gs))
+    args = [dev32(a) for a in (lam, alpha, delta, mu, y)]
+    got = bk.gh_logk_sum(*args, grad_sum=dev32(gs), range="mlp_table", mlp=net)
+    newton = bk.gh_logk_sum(*args, grad_sum=dev32(gs))
+    assert all(bool(torch.isfinite(g).all()) for g in got)
+    pick = np.array([0, 311, 702, 1023])
+    sub = [g[torch.tensor(pick, device="cuda")] for g in got]
+    check_against_reference(sub, lam[pick], alpha[pick], delta[pick], mu[pick], y, gs[pick])
+    # against the Newton bracket on every set: both within the FP32 bar of
+    # the exact sums, so within twice that of each other
+    sc = scales(lam[pick], alpha[pick], delta[pick], mu[pick], y)
+    for k in range(5):
+        d = np.abs(host(got[k]) - host(newton[k]))[pick]
+        g = np.abs(gs[pick]) if k > 0 else 1.0
+        assert np.all(d <= 2e-5 * sc[k] * g), k
+
+
+def test_table_range_forced_fallback_is_the_newton_sum(bk):
+    # zero weights with a t1 margin of -30: every learned bracket fails its
+    # check and takes the Newton bracket in its lane, so the sums are those of
+    # the Newton call bit for bit
+    from paper_2108_11560_amd import mlp as M
+    p = np.zeros(M.NPARAMS, dtype=np.float32)
+    p[M.O_META:M.O_META + 6] = [1.0, 3.0, 0.0, 4.0, -30.0, 0.0]
+    m = M.RangeMLP(p)
+    try:
+        lam, alpha, delta, mu, y, gs = workloads.gh_batch(64, 3000, seed=38, grad_seed=39)
+        args = [dev32(a) for a in (lam, alpha, delta, mu, y)]
+        a = bk.gh_logk_sum(*args, grad_sum=dev32(gs), range="mlp_table", mlp=m)
+        b = bk.gh_logk_sum(*args, grad_sum=dev32(gs))
+        assert all(torch.equal(p_, q_) for p_, q_ in zip(a, b))
+    finally:
+        m.close()
+
+
+def test_table_range_no_alloc_matches(bk, net):
+    lam, alpha, delta, mu, y, gs = workloads.gh_batch(128, 4096, seed=40, grad_seed=41)
+    args = [dev32(a) for a in (lam, alpha, delta, mu, y)]
+    a = bk.gh_logk_sum(*args, grad_sum=dev32(gs), range="mlp_table", mlp=net)
+    b = bk.gh_logk_sum(*args, grad_sum=dev32(gs), range="mlp_table", mlp=net, no_alloc=True)
+    assert all(torch.equal(p_, q_) for p_, q_ in zip(a, b))
+
+
+def test_learned_range_modes_rejected_or_required(bk, net):
+    lam, alpha, delta, mu, y, _ = workloads.gh_batch(4, 100, seed=42)
+    args = [dev32(a) for a in (lam, alpha, delta, mu, y)]
+    with pytest.raises(RuntimeError, match="UNSUPPORTED"):
+        bk.gh_logk_sum(*args, range="mlp", mlp=net)
+    with pytest.raises(RuntimeError, match="RANGE_MODE"):
+        bk.gh_logk_sum(*args, range="mlp_table")

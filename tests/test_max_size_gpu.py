@@ -111,7 +111,7 @@ def test_learned_range_at_its_limit(bk, big_pairs):
         mlp.train(vt, xt, steps=3000, batch=8192, lr=3e-3, lr_final=1e-4, seed=1)
         vc, xc, _ = workloads.scale_pairs(1 << 16, seed=8)
         M.calibrate_margins(mlp, torch.tensor(vc, dtype=torch.float32, device="cuda"),
-                            torch.tensor(xc, dtype=torch.float32, device="cuda"), target_fallback=0.005)
+                            torch.tensor(xc, dtype=torch.float32, device="cuda"), target_fallback=0.001)
 
         vm, xm = v[:N_MLP], x[:N_MLP]
         # one element past the limit: an argument error, nothing launched

@@ -79,3 +79,40 @@ def test_targets_and_bracket_roundtrip():
     assert np.allclose(b0, t0) and np.allclose(b1, t1)
     b0, b1 = M.bracket_from_outputs(y, 0.1, 0.05)
     assert np.all(b1 > t1) and np.all(b0 <= t0)
+
+
+def test_activation_shape():
+    # phi(a) = u (3 - u^2) / 2, u = clamp(a / 1.5, -1, 1): odd, slope 1 at 0,
+    # +-1 from |a| = 1.5 on with a vanishing slope there, increasing, and its
+    # derivative (returned beside it) is the slope of its values
+    a = np.linspace(-4.0, 4.0, 8001)
+    h, d = M.phi(a)
+    assert np.array_equal(M.phi(-a)[0], -h)
+    assert M.phi(0.0)[0] == 0.0 and M.phi(0.0)[1] == 1.0
+    assert np.all(h[a >= 1.5] == 1.0) and np.all(h[a <= -1.5] == -1.0)
+    assert np.all(d[np.abs(a) >= 1.5] == 0.0)
+    assert np.all(np.diff(h) >= 0.0) and np.all(np.abs(h) <= 1.0)
+    eps = 1e-6
+    fd = (M.phi(a + eps)[0] - M.phi(a - eps)[0]) / (2 * eps)
+    assert np.max(np.abs(fd - d)) <= 1e-6
+    # the cubic through (0, 0) and (1.5, 1) with slopes 1 and 0 there
+    assert np.isclose(M.phi(0.75)[0], 0.6875) and np.isclose(M.phi(0.75)[1], 0.75)
+
+
+def test_first_layer_clamp():
+    a = np.array([-3.0, -1.0, -0.999, -0.25, 0.0, 0.5, 0.999, 1.0, 2.0])
+    h, d = M.hard_clamp(a)
+    assert np.array_equal(h, [-1.0, -1.0, -0.999, -0.25, 0.0, 0.5, 0.999, 1.0, 1.0])
+    assert np.array_equal(d, [0, 0, 1, 1, 1, 1, 1, 0, 0])
+    # the network's first layer is the clamp: with W2 = I-like weights read out
+    # through W3, y follows phi(clamp(W1 z + b1)) by hand on one unit
+    p = np.zeros(M.NPARAMS)
+    W1, b1, W2, b2, W3, b3 = M.unpack(p)
+    W1[0] = [2.0, 0.0]
+    W2[0, 0] = 1.0
+    W3[0, 0] = 1.0
+    p = M.pack(W1, b1, W2, b2, W3, b3)
+    z = np.array([[0.3, 5.0], [0.9, -1.0], [-4.0, 0.0]])
+    y, _ = M.forward(p, z)
+    expect = M.phi(np.clip(2.0 * z[:, 0], -1, 1))[0]
+    assert np.allclose(y[:, 0], expect) and np.all(y[:, 1] == 0.0)

@@ -113,3 +113,93 @@ def test_threshold_policy(bk):
     assert bk.set_split_threshold(prev) == 123
     with pytest.raises(bk.BesselError):
         bk.set_split_threshold(-1)
+
+
+# ---- second derivatives on the 16-lane layout ------------------------------
+
+HESS_AGREE = {torch.float64: 1e-12, torch.float32: 2e-6}
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("n", [1, 15, 17, 1000, 4097])
+def test_hess_small_batches_against_oracle(bk, dt, n):
+    v, x, _ = workloads.scale_pairs(n, seed=520 + n)
+    vt, xt = dev(v, dt), dev(x, dt)
+    with threshold(bk, 1 << 20):
+        got = np.stack([host(o) for o in bk.logk_hess(vt, xt)], axis=1)
+    ref = oracle.logk_hess(host(vt), host(xt))
+    err = mixed(got, ref)
+    assert err.max() <= TOL[dt], err.max(axis=0)
+    # the one-lane layout on the same inputs: the same sums in another order
+    with threshold(bk, 0):
+        one = np.stack([host(o) for o in bk.logk_hess(vt, xt)], axis=1)
+    assert mixed(got, one).max() <= HESS_AGREE[dt]
+
+
+def test_hess_split_validated_domain(bk):
+    # the centred FP64 moments on the split layout across the validated
+    # domain (v to 1e3, x in [1e-6, 1e5]), against the oracle at the FP64 bar
+    v, x = workloads.domain_pairs(400, seed=62)
+    vt, xt = dev(v, torch.float64), dev(x, torch.float64)
+    with threshold(bk, 1 << 20):
+        got = np.stack([host(o) for o in bk.logk_hess(vt, xt)], axis=1)
+    ref = oracle.logk_hess(v, x)
+    err = mixed(got, ref)
+    print("split layout, validated domain: max mixed error per output", err.max(axis=0))
+    assert err.max() <= 1e-12
+
+
+def test_hess_split_conventions(bk):
+    nan, inf = float("nan"), float("inf")
+    v = dev([nan, 1.0, 1.0, 1.0, 1.0, inf, -2.5, 0.0], torch.float64)
+    x = dev([1.0, nan, -1.0, 0.0, inf, 2.0, 3.0, 3.0], torch.float64)
+    with threshold(bk, 1 << 20):
+        out = [host(o) for o in bk.logk_hess(v, x)]
+        pos = [host(o) for o in bk.logk_hess(-v[6:7], x[6:7])]
+    assert np.isnan(out[0][:3]).all()
+    assert out[0][3] == inf and out[0][4] == -inf and out[0][5] == inf
+    for o in out[1:]:
+        assert np.isnan(o[:6]).all()
+    # odd in v: d/dv and d2/dvdx flip sign, the rest do not; v = 0 gives 0
+    assert pos[1][0] == -out[1][6] and pos[5][0] == -out[5][6]
+    assert pos[3][0] == out[3][6] and pos[4][0] == out[4][6]
+    assert out[1][7] == 0.0 and out[5][7] == 0.0
+
+
+# ---- learned range modes below the threshold -------------------------------
+
+
+@pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
+@pytest.mark.parametrize("n", [1, 15, 17, 1000, 4097])
+def test_learned_small_batches_take_the_split_newton_path(bk, mode, n):
+    """At most the split threshold, a learned-range call runs the Newton
+    bracket on 16 lanes per element (one launch), so its results are those of
+    the plain FP32 call on the same layout, bit for bit, and the handle
+    reports no fallback."""
+    from paper_2108_11560_amd import mlp as M
+    v, x, _ = workloads.scale_pairs(n, seed=540 + n)
+    vt, xt = dev(v, torch.float32), dev(x, torch.float32)
+    go = dev(workloads.upstream_grad(n, seed=541 + n), torch.float32)
+    # zero weights and a t1 margin of -30: every learned bracket fails its
+    # check, so a call on the fused kernel would count n fallbacks
+    p = np.zeros(M.NPARAMS, dtype=np.float32)
+    p[M.O_META:M.O_META + 6] = [1.0, 3.0, 0.0, 4.0, -30.0, 0.0]
+    mlp = M.RangeMLP(p)
+    try:
+        with threshold(bk, 0):
+            bk.logk(vt, xt, range=mode, mlp=mlp)
+        assert mlp.fallback_count() == n
+        with threshold(bk, 1 << 14):
+            lk = bk.logk(vt, xt, range=mode, mlp=mlp)
+            assert mlp.fallback_count() == 0
+            l2, dv, dx = bk.logk_dv_dx(vt, xt, grad_out=go, range=mode, mlp=mlp)
+            plain = bk.logk(vt, xt)
+            pl2, pdv, pdx = bk.logk_dv_dx(vt, xt, grad_out=go)
+        assert torch.equal(lk, plain) and torch.equal(l2, pl2)
+        assert torch.equal(dv, pdv) and torch.equal(dx, pdx)
+        ref, rdv, rdx = oracle.logk(host(vt), host(xt), deriv=True)
+        assert mixed(host(lk), ref).max() <= 1e-5
+        g = host(go)
+        assert mixed(host(dv), g * rdv).max() <= 1e-5 and mixed(host(dx), g * rdx).max() <= 1e-5
+    finally:
+        mlp.close()
