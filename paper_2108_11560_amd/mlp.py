@@ -13,6 +13,8 @@ owns the handle, initialises weights, and searches the two output margins.
 from __future__ import annotations
 
 import ctypes
+import hashlib
+import json
 import os
 
 import numpy as np
@@ -41,6 +43,54 @@ class TrainCfg(ctypes.Structure):
         ("alpha", ctypes.c_float),
         ("seed", ctypes.c_uint64),
     ]
+
+
+# What a checkpoint's parameter vector means: the network's shape and
+# activations, the order of the parameter vector and its metadata slots.  A
+# file written for another layout is refused.
+LAYOUT = ("2-64-64-2; h1 = clamp(W1 z + b1, -1, 1); h2 = u(3 - u^2)/2, u = clamp((W2 h1 + b2)/1.5, -1, 1); "
+          "y = W3 h2 + b3; params W1(64x2) b1 W2(64x64) b2 W3(2x64) b3, then m_v s_v m_x s_x margin_t1 margin_t0 0 0")
+CHECKPOINT_VERSION = 1
+
+
+def write_checkpoint(path: str, params: np.ndarray, provenance: dict | None) -> None:
+    """Parameters plus a JSON record (layout, version, provenance) in one .npz,
+    readable without unpickling."""
+    arr = np.ascontiguousarray(params, dtype=np.float32)
+    if arr.size != NPARAMS:
+        raise ValueError(f"expected {NPARAMS} parameters")
+    meta = {"layout": LAYOUT, "version": CHECKPOINT_VERSION, "nparams": NPARAMS,
+            "params_sha256": hashlib.sha256(arr.tobytes()).hexdigest(), "provenance": provenance or {}}
+    with open(path, "wb") as fh:  # the exact path, whatever its suffix
+        np.savez(fh, params=arr, meta=np.array(json.dumps(meta, sort_keys=True)))
+
+
+def read_checkpoint(path: str):
+    """(params, provenance) of a file write_checkpoint wrote; raises ValueError
+    for another layout or version, a wrong size, or parameters that do not
+    match their recorded hash."""
+    f = np.load(path, allow_pickle=False)
+    if not isinstance(f, np.lib.npyio.NpzFile):
+        raise ValueError(f"{path}: not a predictor checkpoint (no layout record)")
+    with f:
+        if "meta" not in f or "params" not in f:
+            raise ValueError(f"{path}: not a predictor checkpoint (no layout record)")
+        meta = json.loads(str(f["meta"]))
+        params = np.asarray(f["params"], dtype=np.float32)
+    if meta.get("layout") != LAYOUT or meta.get("version") != CHECKPOINT_VERSION:
+        raise ValueError(f"{path}: written for another network layout or format version")
+    if params.size != NPARAMS or meta.get("nparams") != NPARAMS:
+        raise ValueError(f"{path}: expected {NPARAMS} parameters, found {params.size}")
+    if hashlib.sha256(params.tobytes()).hexdigest() != meta.get("params_sha256"):
+        raise ValueError(f"{path}: parameters do not match their recorded hash")
+    return params, meta["provenance"]
+
+
+def _sha256_of(*tensors) -> str:
+    h = hashlib.sha256()
+    for t in tensors:
+        h.update(np.ascontiguousarray(t.detach().cpu().numpy()).tobytes())
+    return h.hexdigest()
 
 
 def _vp(t):
@@ -84,6 +134,8 @@ class RangeMLP:
         ptr = arr.ctypes.data_as(ctypes.POINTER(ctypes.c_float)) if arr is not None else None
         check(lib.bessel_mlp_create(ptr, NPARAMS, ctypes.byref(h)), "bessel_mlp_create")
         self._h = h
+        # how the parameters came about: training run, labels, margins
+        self.provenance: dict = {}
 
     @property
     def handle(self) -> int:
@@ -119,13 +171,21 @@ class RangeMLP:
         p[O_META + 4] = margin_t1
         p[O_META + 5] = margin_t0
         self.set_params(p)
+        # as stored: FP32 parameters
+        self.provenance["margins"] = {"t1": float(np.float32(margin_t1)), "t0": float(np.float32(margin_t0))}
 
     def save(self, path: str):
-        np.save(path, self.params())
+        """Parameters with the layout record and the provenance (training
+        configuration and seed, hashes of the training inputs and of their
+        Newton labels, margins and their calibration) in one .npz file."""
+        write_checkpoint(path, self.params(), self.provenance)
 
     @classmethod
     def load_file(cls, path: str) -> "RangeMLP":
-        return cls(np.load(path, allow_pickle=False))
+        params, prov = read_checkpoint(path)
+        net = cls(params)
+        net.provenance = prov
+        return net
 
     # training ------------------------------------------------------------
     def train(self, v: torch.Tensor, x: torch.Tensor, steps: int = 2000, batch: int = 8192, lr: float = 3e-3,
@@ -141,6 +201,18 @@ class RangeMLP:
             rc = self._lib.bessel_mlp_train(self._h, ctypes.byref(cfg), v.numel(), _vp(v), _vp(x),
                                             losses.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), _stream(v.device))
         check(rc, "bessel_mlp_train")
+        # the labels are the Newton brackets of the inputs at the FP32 eps,
+        # which bessel_range returns bit for bit
+        from . import bessel_range
+        t0, t1, _, _ = bessel_range(v, x)
+        self.provenance = {
+            "train": {"steps": int(steps), "batch": int(batch), "lr": float(lr), "lr_final": float(lr_final),
+                      "alpha": float(alpha), "seed": int(seed), "beta1": float(beta1), "beta2": float(beta2),
+                      "adam_eps": float(adam_eps), "final_loss": float(losses[steps - 1]) if steps > 0 else None},
+            "inputs": {"n": int(v.numel()), "sha256_v_x": _sha256_of(v, x)},
+            "labels": {"kind": "Newton bracket, FP32 eps", "sha256_t0_t1": _sha256_of(t0, t1)},
+            "library": self._lib.bessel_version().decode(errors="replace"),
+        }
         return losses[:steps]
 
     def loss_grad(self, v, x, t0, t1, alpha: float = 4.0):
@@ -174,7 +246,7 @@ class RangeMLP:
         return c.value
 
 
-def calibrate_margins(mlp: RangeMLP, v: torch.Tensor, x: torch.Tensor, target_fallback: float = 0.005,
+def calibrate_margins(mlp: RangeMLP, v: torch.Tensor, x: torch.Tensor, target_fallback: float = 0.001,
                       grid_t1=(0.0, 0.01, 0.02, 0.04, 0.07, 0.1, 0.15, 0.2, 0.3),
                       grid_t0=(0.0, 0.01, 0.02, 0.04, 0.07, 0.1), range: str = "mlp"):
     """Smallest (margin_t1, margin_t0) on the grid whose fallback rate on (v, x)
@@ -197,4 +269,7 @@ def calibrate_margins(mlp: RangeMLP, v: torch.Tensor, x: torch.Tensor, target_fa
         *_, fb = bessel_range(v, x, range=range, mlp=mlp, want_fallback=True)
         best = (m1, m0, float(fb.float().mean()))
     mlp.set_margins(best[0], best[1])
+    mlp.provenance["calibration"] = {"target_fallback": float(target_fallback), "range": range,
+                                     "n": int(v.numel()), "sha256_v_x": _sha256_of(v, x),
+                                     "fallback_rate": best[2]}
     return best
