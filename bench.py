@@ -54,18 +54,20 @@ import workloads  # noqa: E402
 # Per FP64 node: t 1, cosh 1, argument 2, exp 12 (clamp 1, reduction 4,
 # degree-3 polynomial 3, table index 1, table product 1, 2^k 2; the table read
 # is an LDS load), sum 1, u 1, e^{+-t} 2, re-anchoring 1.5 (= 21.5), + 6 with
-# d/dv and d/dx, + 6 more for the second derivatives.  W_PRE: peak 120, G 80, t1 50, t0 60, bin set-up 120, final log
-# and reciprocal 50, loads 20.  Keyed by (dtype, derivative order): 0 log K,
-# 1 with d/dv and d/dx, 2 with the second derivatives too.
+# d/dv and d/dx, + 12 more for the second derivatives (six moments about the
+# peak, two operations each).  W_PRE: peak 120, G 80, t1 50, t0 60, bin set-up
+# 120, final log and reciprocal 50, loads 20.  Keyed by (dtype, derivative
+# order): 0 log K, 1 with d/dv and d/dx, 2 with the second derivatives too.
 W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
-          ("f64", 0): 21.5, ("f64", 1): 27.5, ("f64", 2): 33.5}
+          ("f64", 0): 21.5, ("f64", 1): 27.5, ("f64", 2): 39.5}
 W_PRE = 500.0
-# Learned bracket: the network's VALU work (128 activations 1 / (1 + 2^a) at
-# 5 slots, bf16 packing of the 128 activations two per instruction 64,
-# features 6, outputs 4; its three layers' 56 MFMAs per 64 elements run on the
-# matrix cores and are not counted) plus bracket 10, shift 35, bin set-up 120,
-# check 10, final 50, loads 30.
-W_NET = 714.0
+# Learned bracket: the network's VALU work (64 first-layer clamps, two per
+# f16 conversion with its clamp bit, 32; 64 second-layer cubics, two per
+# packed group of 4 instructions -- conversion with clamp, one FMA, two
+# products -- 128; features 6, outputs 4; its three layers' 56 MFMAs per 64
+# elements run on the matrix cores and are not counted) plus bracket 10, shift
+# 35, bin set-up 120, check 10, final 50, loads 30.
+W_NET = 170.0
 W_MLP_PRE = W_NET + 255.0
 # The same network read from its bilinear table: features 8, cell index 12,
 # two 16-byte loads, 6 FMAs, in place of the network's VALU work.
@@ -78,12 +80,20 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 
 # HBM bytes per element of the learned-range call (fused kernel + fallback)
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
-# its size on this counter) plus WRITE_SIZE, taken on the sources the two
-# kernels are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "a9c23611e735497ea8b798ff1ee56ea6ed6ee05a469269461b5b0cc5048fce36",
-           # fused (65676 * 2 + 65804 KiB) + fallback (717 * 2 + 164 KiB) per 2^24 elements
-           "bytes_per_elem": 12.131}
-TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp")
+# its size on this counter) plus WRITE_SIZE, taken on the sources the kernels
+# are compiled from (hashed below); reported only while they still match.
+TRAFFIC = {"sources_sha256": "07e62ee12cfeb30131893cf667978a5e703745ad5654d1aca40cac3f12ecd022",
+           # fused (65673 * 2 + 65629 KiB) + fallback (277 * 2 + 56 KiB) per 2^24 elements
+           "bytes_per_elem": 12.060}
+TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp", "bessel_learned.hpp",
+                   "bessel_kernels.hip", "bessel_gh.hip")
+# FP32 transcendental instructions (v_exp/log/rcp/sqrt_f32) per element, from
+# the SQ_INSTS_VALU_TRANS_F32 counter per wavefront of 64 elements on the same
+# sources (the FP64 paths' come from the FP32 bracket search; their
+# exponentials and logarithms are FP64 software)
+TRANS_F32_PER_ELEM = {"f32_fwd": 194, "f32_fwd_bwd": 195, "f32_hess": 195, "f64_fwd": 64, "f64_fwd_bwd": 64,
+                      "f64_hess": 64, "f32_mlp_fwd": 144, "f32_mlp_fwd_bwd": 145, "f32_mlp_table_fwd": 144,
+                      "f32_mlp_table_fwd_bwd": 145, "gh_f32_fwd_bwd": 166}
 
 
 def kernel_sources_sha256() -> str:
@@ -122,7 +132,9 @@ def parse():
     p.add_argument("--copy-check", action="store_true",
                    help="also run a plain 256 MiB device copy (calibrates the FETCH_SIZE / WRITE_SIZE counters)")
     p.add_argument("--no-sweep", action="store_true", help="skip the batch-size sweep")
-    p.add_argument("--save-mlp", default=None, help="write the trained, calibrated predictor (.npy)")
+    p.add_argument("--no-configs", action="store_true",
+                   help="skip the per-configuration block (plain 4096 FP64, differentiation 2^22, GH sums)")
+    p.add_argument("--save-mlp", default=None, help="write the trained, calibrated predictor (.npz checkpoint with its provenance)")
     p.add_argument("--load-mlp", default=None,
                    help="use a predictor saved by --save-mlp instead of training one (for counter runs, "
                         "which serialise every dispatch)")
@@ -217,6 +229,88 @@ def cpu_baseline(v, x, v32, x32, gpu, budget_s):
 WARM_S = 0.05
 
 
+def err_stats(got, ref) -> dict:
+    """Mixed error |got - ref| / max(1, |ref|): max, 99.9th percentile, median."""
+    e = np.abs(np.asarray(got, np.float64) - ref) / np.maximum(1.0, np.abs(ref))
+    return {"max": float(e.max()), "p99.9": float(np.quantile(e, 0.999)), "median": float(np.median(e))}
+
+
+def oracle_timed(fn):
+    """(result, seconds) of one oracle call on the host cores."""
+    t0 = time.perf_counter()
+    out = fn()
+    return out, time.perf_counter() - t0
+
+
+def per_config(bk, mlp, nb, steps, warmup, paths, dev):
+    """One entry per workload configuration: the GPU path's throughput at its
+    own size, its error against the oracle (max / p99.9 / median mixed error)
+    on all or a stratified part of its elements, and the oracle's own rate on
+    that part (the CPU baseline, host cores; a baseline only)."""
+    import torch
+
+    import oracle
+    from oracle import gh_ref
+    threads = oracle.default_threads()
+    out = {}
+    # plain method, FP64, 4096 pairs (seed 0), Newton bracket: every pair checked
+    v, x = workloads.plain_pairs(4096, seed=0)
+    vt, xt = torch.tensor(v, device=dev), torch.tensor(x, device=dev)
+    ms = time_path(lambda: bk.logk(vt, xt, nbins=nb), steps, warmup)
+    got = bk.logk(vt, xt, nbins=nb).cpu().numpy()
+    ref, sec = oracle_timed(lambda: oracle.logk(v, x, nthreads=threads))
+    out["plain-fp64-4096"] = {"n": 4096, "dtype": "f64", "us_per_call": 1e3 * ms, "evals_per_s": 4096 / (ms * 1e-3),
+                              "err_vs_oracle": err_stats(got, ref), "oracle_elements": 4096,
+                              "cpu_oracle_evals_per_s": 4096 / sec, "cpu_cores": threads}
+    # differentiation, 2^22 pairs as the scale workload (seed 3), fwd + bwd with
+    # upstream gradients (seed 13), FP32 and FP64; oracle on 2^13 stratified pairs
+    n3 = 1 << 22
+    v, x, strata = workloads.scale_pairs(n3, seed=3)
+    go = workloads.upstream_grad(n3, seed=13)
+    idx = workloads.stratified_subset(strata, 1 << 13, seed=11)
+    entry = {"n": n3}
+    for dt, tdt in (("f64", torch.float64), ("f32", torch.float32)):
+        vt, xt, gt = (torch.tensor(a, dtype=tdt, device=dev) for a in (v, x, go))
+        fn = lambda: bk.logk_dv_dx(vt, xt, grad_out=gt, nbins=nb)  # noqa: E731
+        ms = time_path(fn, max(1, steps // 2), warmup)
+        lk, dv, dx = (t.double().cpu().numpy()[idx] for t in fn())
+        vs, xs = vt.double().cpu().numpy()[idx], xt.double().cpu().numpy()[idx]
+        (rl, rv, rx), sec = oracle_timed(lambda: oracle.logk(vs, xs, deriv=True, nthreads=threads))
+        g = gt.double().cpu().numpy()[idx]
+        entry[dt] = {"ms": ms, "evals_per_s": n3 / (ms * 1e-3), "err_vs_oracle": {
+            "logk": err_stats(lk, rl), "grad_v": err_stats(dv, g * rv), "grad_x": err_stats(dx, g * rx)}}
+        entry["oracle_elements"] = int(idx.size)
+        entry["cpu_oracle_evals_per_s"] = idx.size / sec
+    entry["cpu_cores"] = threads
+    out["diff-2^22"] = entry
+    # GH-shaped per-set sums: 1024 sets x 65536 samples, fwd + bwd, FP32, with
+    # the Newton bracket and with the network's table; the oracle sums every
+    # set over the first 256 samples (GPU sums of the same sub-batch)
+    lam, alpha, delta, mu, y, gs = workloads.gh_batch(1024, 65536, seed=5, grad_seed=15)
+    f32 = lambda a: torch.tensor(a, dtype=torch.float32, device=dev)  # noqa: E731
+    args = [f32(a) for a in (lam, alpha, delta, mu, y)]
+    entry = {"sets": 1024, "samples": 65536}
+    n5 = 1024 * 65536
+    sub = [f32(a) for a in (lam, alpha, delta, mu, y[:256])]
+    hl = lambda a: a.double().cpu().numpy()  # noqa: E731
+    ref, sec = oracle_timed(lambda: gh_ref.gh_sums(*(hl(a) for a in sub), hl(f32(gs)), nthreads=threads))
+    for name, kw in (("newton", {}), ("mlp_table", {"range": "mlp_table", "mlp": mlp})):
+        ms = time_path(lambda: bk.gh_logk_sum(*args, grad_sum=f32(gs), nbins=nb, **kw), max(1, steps // 4),
+                       max(1, warmup))
+        got = [hl(t) for t in bk.gh_logk_sum(*sub, grad_sum=f32(gs), nbins=nb, **kw)]
+        # per-set relative error of the sum and of each gradient, against the
+        # summed magnitudes of the terms (the natural scale of a sum's rounding)
+        scale = [np.maximum(1.0, np.abs(r)) for r in ref]
+        entry[name] = {"ms": ms, "evals_per_s": n5 / (ms * 1e-3), "err_vs_oracle_relative": {
+            k: err_stats(np.asarray(got[i]) / scale[i], np.asarray(ref[i]) / scale[i])
+            for i, k in enumerate(("sum", "d_lambda", "d_alpha", "d_delta", "d_mu"))}}
+    entry["oracle_elements"] = 1024 * 256
+    entry["cpu_oracle_evals_per_s"] = 1024 * 256 / sec
+    entry["cpu_cores"] = threads
+    out["gh-1024x65536"] = entry
+    return out
+
+
 def main():
     global WARM_S
     args = parse()
@@ -264,7 +358,7 @@ def main():
         vca, xca, _ = workloads.scale_pairs(1 << 16, seed=8)
         m1, m0, cal_rate = M.calibrate_margins(mlp, torch.tensor(vca, dtype=torch.float32, device=dev),
                                                torch.tensor(xca, dtype=torch.float32, device=dev),
-                                               target_fallback=0.005)
+                                               target_fallback=0.001)
     if args.save_mlp:
         mlp.save(args.save_mlp)
     torch.cuda.synchronize()
@@ -330,6 +424,11 @@ def main():
         else:
             p["alg_slots_per_elem"] = alg_slots(key[:3], der, nb)
         p["valu_frac"] = p["alg_slots_per_elem"] * p["evals_per_s"] / PEAK_SLOTS
+    if TRAFFIC["sources_sha256"] == kernel_sources_sha256():
+        for key, p in paths.items():
+            if key in TRANS_F32_PER_ELEM:
+                p["trans_f32_per_elem"] = TRANS_F32_PER_ELEM[key]
+                p["trans_f32_per_s"] = TRANS_F32_PER_ELEM[key] * p["evals_per_s"]
 
     head = paths["f32_mlp_fwd"]
     achieved = head["alg_slots_per_elem"] * head["evals_per_s"]
@@ -411,6 +510,8 @@ def main():
                           "note": "about 5 ms per call, flat from 10 to 1e4 elements (Section 3.4); 2e6 evals/s "
                                   "would follow at 1e4 elements"},
     }
+    if not args.no_configs:
+        line["configs"] = per_config(bk, mlp, nb, args.steps, args.warmup, paths, dev)
     if not args.no_cpu:
         gpu = {
             "f64": bk.logk(V["f64"], X["f64"], nbins=nb).cpu().numpy(),
