@@ -202,6 +202,38 @@ def test_finite_difference_1024(bk):
     assert np.all(np.abs(dx - fd_x) <= 1e-8 * np.maximum(1.0, np.abs(dx)) + noise / hx)
 
 
+def test_finite_difference_richardson_1024(bk):
+    # The same 1024 pairs with a step the rounding noise does not swamp:
+    # central differences at h and h/2 combined by Richardson extrapolation
+    # (truncation O(h^4) ~ 1e-12), h = 1e-3 in v and 1e-3 x in x.  The noise
+    # term (a few eps of the largest cancelled term, over the step, times 3
+    # for the extrapolation) is then ~1e-9 even at x ~ 1e3, so the bound
+    # binds where the 1e-6 step above cannot.
+    v, x, _ = workloads.scale_pairs(1 << 22, seed=3)
+    v, x = v[:1024], x[:1024]
+    dt = torch.float64
+    f = lambda a, b: host(bk.logk(to_dev(a, dt), to_dev(b, dt)))  # noqa: E731
+    lk = f(v, x)
+    _, dv, dx = bk.logk_dv_dx(to_dev(v, dt), to_dev(x, dt))
+    dv, dx = host(dv), host(dx)
+
+    def rich(g, z, hz):
+        d1 = (g(z + hz) - g(z - hz)) / (2 * hz)
+        d2 = (g(z + hz / 2) - g(z - hz / 2)) / hz
+        return (4 * d2 - d1) / 3
+
+    h = 1e-3
+    fd_v = rich(lambda a: f(np.abs(a), x), v, h)  # log K is even in v
+    fd_x = rich(lambda b: f(v, b), x, h * x)
+    tp, _, _, _ = oracle.range_exact(v, x, LOG_EPS[dt])
+    noise = 1e-15 * (1.0 + np.abs(lk) + v * tp + x * np.cosh(tp))
+    ev = np.abs(dv - fd_v) - 3 * noise / h
+    ex = np.abs(dx - fd_x) - 3 * noise / (h * x)
+    print("Richardson FD: max |dv - fd| %.2e, max |dx - fd| %.2e" % (np.abs(dv - fd_v).max(), np.abs(dx - fd_x).max()))
+    assert np.all(ev <= 1e-9 * np.maximum(1.0, np.abs(dv)))
+    assert np.all(ex <= 1e-9 * np.maximum(1.0, np.abs(dx)))
+
+
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_range_invariants(bk, dt):
     v, x, strata = workloads.scale_pairs(1 << 16, seed=1)
