@@ -51,17 +51,18 @@ import workloads  # noqa: E402
 # count of the formulation.  Per FP32 node: argument 1, conversion 1, exp2 2,
 # widening 1, sum 1, u 1, linear part 1, cosh recurrence 1 (= 9); with d/dv and
 # d/dx + r, t, w r, w u and two sums (= 15); second derivatives + 6 (= 21).
-# Per FP64 node: t 1, 2 (cosh t - 1) as a product 1, argument 2, exp 12 (clamp
-# 1, reduction 4, degree-3 polynomial 3, table index 1, table product 1, 2^k 2;
-# the table read is an LDS load), sum 1, u 1, the two expm1 recurrences 2,
-# re-anchoring 1.5 (= 21.5), + 5 with d/dv and d/dx (r, w r, w u, two sums),
+# Per FP64 node: 2 (cosh t - 1) as a product 1, argument 2 (v t - G advanced by
+# one FMA, then the cosh term), exp 12 (clamp 1, reduction 4, degree-3
+# polynomial 3, table index 1, table product 1, 2^k 2; the table read is an
+# LDS load), sum 1, u 1, the two expm1 recurrences 2, re-anchoring 1.5
+# (= 20.5), + 6 with d/dv and d/dx (t by addition, r, w r, w u, two sums),
 # + 13 more for the second derivatives (cosh t - 1 from the product, six
 # moments about the peak, two operations each).  W_PRE: peak 120, G 80, t1 50,
 # t0 60, bin set-up 120, final log and reciprocal 50, loads 20.  Keyed by
 # (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2 with the second
 # derivatives too.
 W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
-          ("f64", 0): 21.5, ("f64", 1): 26.5, ("f64", 2): 39.5}
+          ("f64", 0): 20.5, ("f64", 1): 26.5, ("f64", 2): 39.5}
 W_PRE = 500.0
 # Learned bracket: the network's VALU work (64 first-layer clamps, two per
 # f16 conversion with its clamp bit, 32; 64 second-layer cubics, two per

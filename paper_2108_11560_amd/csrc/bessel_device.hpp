@@ -419,14 +419,14 @@ constexpr int kChunk = 16;    // nodes per unrolled chunk (FP64 bins)
 constexpr int kChunk32 = 32;  // nodes per unrolled chunk (FP32 bins)
 
 // Second-order moments of one FP64 node (DER == 2), about the centres a (t)
-// and b (cosh t; C and b may both be given less 1): with wu = e^{A} u (f) and
-// wr = e^{A} r (d/dv f / t),
-//   M0 += wu (t - a)^2,  M1 += wu (C - b)^2,  M2 += wr t (C - b),
-//   M3 += wu (t - a),    M4 += wu (C - b),    M5 += (wu - wr) t.
+// and b (cosh t; C and b may both be given less 1): with wu = e^{A} u (f),
+// wr = e^{A} r (d/dv f / t) and d = t - a (formed by the caller),
+//   M0 += wu d^2,  M1 += wu (C - b)^2,  M2 += wr t (C - b),
+//   M3 += wu d,    M4 += wu (C - b),    M5 += (wu - wr) t.
 // Six sums, 12 operations a node against 6 for the raw moments t^2 f,
 // C^2 f, t C d/dv f; each sum is its own chain, so no even/odd split.
-__device__ __forceinline__ void moments(double wu, double wr, double t, double C, double a, double b, double* M) {
-  const double Y = C - b, d = t - a;
+__device__ __forceinline__ void moments(double wu, double wr, double t, double d, double C, double b, double* M) {
+  const double Y = C - b;
   const double wuY = wu * Y, wud = wu * d;
   M[1] = fma(wuY, Y, M[1]);
   M[4] += wuY;
@@ -448,6 +448,13 @@ __device__ __forceinline__ void moments(double wu, double wr, double t, double C
 // e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the FP32
 // bins); even and odd nodes are summed apart (independent FMA chains).
 // S_x = sum f cosh t is returned as S0 + sum f (cosh t - 1).
+// Along a chunk, v t - (g(t_p) + x) - log 2 advances by fma(v, h, .), t and
+// t - ca by adding h, from the chunk's first node (one operation each, no
+// per-node constant b h to materialise).  Each step rounds by at most half an
+// ulp of the running value, so after the kChunk - 1 steps the error is of the
+// order of v ulp(t), which the direct form v (t_a + b h) carries at every
+// node; t - ca, small near the peak, keeps a finer ulp than t - ca formed
+// from t.
 // DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums,
 // taken about the centres ca (for t) and 1 + cb1 (for cosh t): the caller
 // passes the peak and its cosh - 1, within a few widths of the integrand's
@@ -472,18 +479,23 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
     Expm1Pair an = expm1_pair(ta);
+    double L = fma(v, ta, -Gs), t = ta, d = ta - ca;
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
-      const double t = fma((double)b, h, ta);
+      if (b > 0) {
+        L = fma(v, h, L);  // an explicit FMA, whatever the compiler's contraction
+        if (GRAD) t += h;
+        if (DER >= 2) d += h;
+      }
       const double P = an.ep * an.em;  // 2 (cosh t - 1)
-      double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
+      double w = exp_node_f64(fma(-xh, P, L));
       if (b == 0) w *= (c == 0) ? 0.5 : 1.0;
       S[b & 1] = fma(w, u, S[b & 1]);
       if (GRAD) {
         const double wr = w * r, wu = w * u;
         Sv[b & 1] = fma(wr, t, Sv[b & 1]);
         Sx[b & 1] = fma(wu, P, Sx[b & 1]);
-        if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
+        if (DER >= 2) moments(wu, wr, t, d, 0.5 * P, cb1, M);
         r = fma(r, Q, E2);
       }
       u = fma(u, Q, E2);
@@ -503,7 +515,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
       const double wr = w * r, wu = w * u;
       Sv[m & 1] = fma(wr, t, Sv[m & 1]);
       Sx[m & 1] = fma(wu, P, Sx[m & 1]);
-      if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
+      if (DER >= 2) moments(wu, wr, t, t - ca, 0.5 * P, cb1, M);
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
@@ -723,7 +735,7 @@ __device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool
       const double wr = w * r, wu = w * u;
       s.Sv = fma(wr, t, s.Sv);
       SxP = fma(wu, P, SxP);
-      if (DER >= 2) moments(wu, wr, t, 0.5 * P, ca, cb1, M);
+      if (DER >= 2) moments(wu, wr, t, t - ca, 0.5 * P, cb1, M);
       r = fma(r, Q, E2);
     }
     u = fma(u, Q, E2);
