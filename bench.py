@@ -85,9 +85,9 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the kernels
 # are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "07e62ee12cfeb30131893cf667978a5e703745ad5654d1aca40cac3f12ecd022",
-           # fused (65673 * 2 + 65629 KiB) + fallback (277 * 2 + 56 KiB) per 2^24 elements
-           "bytes_per_elem": 12.060}
+TRAFFIC = {"sources_sha256": "c89fa4624bfaafe2846c339eebe60a0d898221db4a2543c93f7582f4adca8f1d",
+           # fused (65673 * 2 + 65628 KiB) + fallback (272 * 2 + 56 KiB) per 2^24 elements
+           "bytes_per_elem": 12.059}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp", "bessel_learned.hpp",
                    "bessel_kernels.hip", "bessel_gh.hip")
 # FP32 transcendental instructions (v_exp/log/rcp/sqrt_f32) per element, from

@@ -109,11 +109,17 @@ int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void* x, const 
  * bessel_range -- the bracket of Section 2.1 (Eq. (7)-(8)) for the dtype's eps:
  *   t0[i], t1[i]    integration limits; [t0, t1] contains every t with
  *                   g(t) >= g(t_p) + log eps (a superset, never a subset);
- *   tp[i]           (nullable) peak location t_p (Section 2.2);
- *   logf_peak[i]    (nullable) g at the returned t_p, the shift of Eq. (int);
+ *   tp[i]           (nullable) BESSEL_RANGE_NEWTON: the peak location t_p
+ *                   (Section 2.2, FP32 Newton steps);
+ *   logf_peak[i]    (nullable) BESSEL_RANGE_NEWTON: g(t_p), the shift of Eq. (int);
  *   fallback[i]     (nullable, uint8) with a learned range mode: 1 where the
  *                   learned bracket failed its check and the Newton bracket was used.
- * With a learned range mode, tp and logf_peak are those of the bracket actually used.
+ * With a learned range mode, where an element's learned bracket passed its check,
+ * tp is not the peak but the point of the bracket whose g is the shift (the
+ * best of the bracket's midpoint, asinh(v/x) clamped into the bracket and, if
+ * t0 = 0, 0), and logf_peak is g there, in FP32: a lower bound of max g (any
+ * finite shift gives the same log K).  Where the element fell back, all four
+ * outputs are the Newton bracket's.
  */
 int bessel_range(int dtype, int64_t n, const void* v, const void* x, void* t0, void* t1,
                  void* tp, void* logf_peak, int range_mode, const bessel_mlp* mlp,

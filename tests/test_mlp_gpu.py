@@ -272,6 +272,32 @@ def test_learned_range_domain_conventions(mods, trained, mode):
     assert lk[6] == lk[7]
 
 
+@pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
+def test_learned_range_reports_its_shift(mods, trained, mode):
+    """bessel_range in a learned mode: where the learned bracket passed its
+    check, tp is the point of the bracket whose g is the shift and logf_peak
+    is g there (a lower bound of the exact max g); where it fell back, all
+    four outputs are the Newton bracket's."""
+    bk, _ = mods
+    mlp, _ = trained
+    v, x, _ = workloads.scale_pairs(8192, seed=409)
+    v32, x32 = v.astype(np.float32), x.astype(np.float32)
+    vt, xt = dev32(v32), dev32(x32)
+    t0, t1, tp, gp, fb = (host(t) for t in bk.bessel_range(vt, xt, range=mode, mlp=mlp, want_fallback=True))
+    n0, n1, ntp, ngp = (host(t) for t in bk.bessel_range(vt, xt))
+    acc = fb == 0
+    assert acc.mean() > 0.99
+    for a, b in ((t0, n0), (t1, n1), (tp, ntp), (gp, ngp)):
+        assert np.array_equal(a[~acc], b[~acc])
+    vd, xd, tpd = v32.astype(np.float64), x32.astype(np.float64), tp.astype(np.float64)
+    assert (tp[acc] >= t0[acc]).all() and (tp[acc] <= t1[acc]).all()
+    g = np.logaddexp(vd * tpd, -vd * tpd) - np.log(2.0) - xd * np.cosh(tpd)
+    scale = 1.0 + np.abs(g) + vd * tpd + xd * np.cosh(tpd)
+    assert np.max((np.abs(gp - g) / scale)[acc]) <= 1e-5
+    _, G, _, _ = oracle.range_exact(vd, xd, LOG_EPS32)
+    assert np.max(((gp - G) / scale)[acc]) <= 1e-5
+
+
 def test_checkpoint_roundtrip(mods, trained, tmp_path):
     bk, M = mods
     mlp, _ = trained
