@@ -296,14 +296,14 @@ def per_config(bk, mlp, nb, steps, warmup, paths, dev):
     n5 = 1024 * 65536
     sub = [f32(a) for a in (lam, alpha, delta, mu, y[:256])]
     hl = lambda a: a.double().cpu().numpy()  # noqa: E731
-    ref, sec = oracle_timed(lambda: gh_ref.gh_sums(*(hl(a) for a in sub), hl(f32(gs)), nthreads=threads))
+    (ref, scale), sec = oracle_timed(lambda: gh_ref.gh_sums(*(hl(a) for a in sub), hl(f32(gs)), nthreads=threads,
+                                                            with_scales=True))
     for name, kw in (("newton", {}), ("mlp_table", {"range": "mlp_table", "mlp": mlp})):
         ms = time_path(lambda: bk.gh_logk_sum(*args, grad_sum=f32(gs), nbins=nb, **kw), max(1, steps // 4),
                        max(1, warmup))
         got = [hl(t) for t in bk.gh_logk_sum(*sub, grad_sum=f32(gs), nbins=nb, **kw)]
-        # per-set relative error of the sum and of each gradient, against the
-        # summed magnitudes of the terms (the natural scale of a sum's rounding)
-        scale = [np.maximum(1.0, np.abs(r)) for r in ref]
+        # per-set error of the sum and of each gradient relative to the summed
+        # magnitudes of the terms (the natural scale of a sum's rounding)
         entry[name] = {"ms": ms, "evals_per_s": n5 / (ms * 1e-3), "err_vs_oracle_relative": {
             k: err_stats(np.asarray(got[i]) / scale[i], np.asarray(ref[i]) / scale[i])
             for i, k in enumerate(("sum", "d_lambda", "d_alpha", "d_delta", "d_mu"))}}

@@ -21,7 +21,10 @@ import numpy as np
 import oracle
 
 
-def gh_sums(lam, alpha, delta, mu, y, gsum=None, nthreads=None):
+def gh_sums(lam, alpha, delta, mu, y, gsum=None, nthreads=None, with_scales=False):
+    """(S, dS/dlambda, dS/dalpha, dS/ddelta, dS/dmu) per set; with_scales also
+    returns, per output, sum_j max(1, |term_j|) (times |g_i| for the gradients):
+    the natural scale of a sum's rounding, for tolerances."""
     lam, alpha, delta, mu = (np.asarray(a, dtype=np.float64) for a in (lam, alpha, delta, mu))
     y = np.asarray(y, dtype=np.float64)
     S = lam.size
@@ -36,7 +39,12 @@ def gh_sums(lam, alpha, delta, mu, y, gsum=None, nthreads=None):
     g_alpha = np.array([math.fsum(row) for row in dx * r])
     g_delta = np.array([math.fsum(row) for row in dx * alpha[:, None] * delta[:, None] / r])
     g_mu = np.array([math.fsum(row) for row in dx * alpha[:, None] * (-dy) / r])
+    terms = (lk, dv, dx * r, dx * alpha[:, None] * delta[:, None] / r, dx * alpha[:, None] * (-dy) / r)
+    sc = [np.maximum(1.0, np.abs(t)).sum(axis=1) for t in terms]
     if gsum is not None:
         g = np.asarray(gsum, dtype=np.float64)
         g_lam, g_alpha, g_delta, g_mu = g * g_lam, g * g_alpha, g * g_delta, g * g_mu
+        sc = sc[:1] + [np.abs(g) * c for c in sc[1:]]
+    if with_scales:
+        return (out, g_lam, g_alpha, g_delta, g_mu), sc
     return out, g_lam, g_alpha, g_delta, g_mu

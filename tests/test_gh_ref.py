@@ -29,3 +29,15 @@ def test_order_symmetry():
     b = gh_ref.gh_sums(1.0 - lam, alpha, delta, mu, y)
     assert np.allclose(a[0], b[0], rtol=1e-15, atol=0)
     assert np.allclose(a[1], -b[1], rtol=1e-13, atol=1e-15)
+
+
+def test_scales_bound_the_sums():
+    # sum_j max(1, |term_j|) >= |sum_j term_j| (with |g| on the gradients), and
+    # asking for the scales leaves the sums as they are
+    lam, alpha, delta, mu, y, g = workloads.gh_batch(nsets=6, nsamp=11, seed=33)
+    plain = gh_ref.gh_sums(lam, alpha, delta, mu, y, g)
+    sums, sc = gh_ref.gh_sums(lam, alpha, delta, mu, y, g, with_scales=True)
+    for k in range(5):
+        assert np.array_equal(plain[k], sums[k])
+        assert np.all(sc[k] >= np.abs(sums[k]) * (1 - 1e-12))
+    assert np.all(sc[0] >= y.size)
