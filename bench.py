@@ -57,13 +57,13 @@ import workloads  # noqa: E402
 # LDS load), sum 1, u 1, the two expm1 recurrences 2, re-anchoring 1.5
 # (= 20.5), + 6 with d/dv and d/dx (t by addition, r, w r, w u, two sums),
 # + 13 more for the second derivatives (cosh t - 1 from the product, six
-# moments about the peak, two operations each).  W_PRE: peak 120, G 80, t1 50,
-# t0 60, bin set-up 120, final log and reciprocal 50, loads 20.  Keyed by
-# (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2 with the second
-# derivatives too.
+# moments about the peak, two operations each).  W_PRE: peak (4 Newton steps)
+# 100, G (FP64 80, FP32 20), t1 50, t0 60, bin set-up 120, final log and
+# reciprocal 50, loads 20.  Keyed by (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2
+# with the second derivatives too.
 W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
           ("f64", 0): 20.5, ("f64", 1): 26.5, ("f64", 2): 39.5}
-W_PRE = 500.0
+W_PRE = {"f32": 420.0, "f64": 480.0}
 # Learned bracket: the network's VALU work (64 first-layer clamps, two per
 # f16 conversion with its clamp bit, 32; 64 second-layer cubics, two per
 # packed group of 4 instructions -- conversion with clamp, one FMA, two
@@ -85,17 +85,17 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the kernels
 # are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "c89fa4624bfaafe2846c339eebe60a0d898221db4a2543c93f7582f4adca8f1d",
-           # fused (65673 * 2 + 65628 KiB) + fallback (272 * 2 + 56 KiB) per 2^24 elements
-           "bytes_per_elem": 12.059}
+TRAFFIC = {"sources_sha256": "f5d3b7c962abdca104cac79dfca3a69b40445244762f9a1a10b30e4e028f97ea",
+           # fused (65672 * 2 + 65623 KiB) + fallback (251 * 2 + 52 KiB) per 2^24 elements
+           "bytes_per_elem": 12.056}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp", "bessel_learned.hpp",
                    "bessel_kernels.hip", "bessel_gh.hip")
 # FP32 transcendental instructions (v_exp/log/rcp/sqrt_f32) per element, from
 # the SQ_INSTS_VALU_TRANS_F32 counter per wavefront of 64 elements on the same
 # sources (the FP64 paths' come from the FP32 bracket search; their
 # exponentials and logarithms are FP64 software)
-TRANS_F32_PER_ELEM = {"f32_fwd": 194, "f32_fwd_bwd": 195, "f32_hess": 195, "f64_fwd": 64, "f64_fwd_bwd": 64,
-                      "f64_hess": 64, "f32_mlp_fwd": 144, "f32_mlp_fwd_bwd": 145, "f32_mlp_table_fwd": 144,
+TRANS_F32_PER_ELEM = {"f32_fwd": 191, "f32_fwd_bwd": 192, "f32_hess": 192, "f64_fwd": 59, "f64_fwd_bwd": 59,
+                      "f64_hess": 59, "f32_mlp_fwd": 144, "f32_mlp_fwd_bwd": 145, "f32_mlp_table_fwd": 144,
                       "f32_mlp_table_fwd_bwd": 145, "gh_f32_fwd_bwd": 166}
 
 
@@ -110,7 +110,7 @@ def kernel_sources_sha256() -> str:
 
 
 def alg_slots(dt: str, der: int, nbins: int) -> float:
-    return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE
+    return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE[dt]
 
 
 def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float, pre: float = W_MLP_PRE) -> float:

@@ -111,7 +111,9 @@ int bessel_logk_dv_dx(int dtype, int64_t n, const void* v, const void* x, const 
  *                   g(t) >= g(t_p) + log eps (a superset, never a subset);
  *   tp[i]           (nullable) BESSEL_RANGE_NEWTON: the peak location t_p
  *                   (Section 2.2, FP32 Newton steps);
- *   logf_peak[i]    (nullable) BESSEL_RANGE_NEWTON: g(t_p), the shift of Eq. (int);
+ *   logf_peak[i]    (nullable) BESSEL_RANGE_NEWTON: g(t_p), the shift of Eq. (int)
+ *                   (BESSEL_F32: evaluated in FP32 arithmetic as the F32 kernels
+ *                   shift by it, to ~1e-6 of log cosh(v t_p) + x cosh t_p);
  *   fallback[i]     (nullable, uint8) with a learned range mode: 1 where the
  *                   learned bracket failed its check and the Newton bracket was used.
  * With a learned range mode, where an element's learned bracket passed its check,

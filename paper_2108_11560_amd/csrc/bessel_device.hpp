@@ -125,6 +125,18 @@ __device__ __forceinline__ double one_minus_exp_neg(double z) {
   return (e.k == 0) ? -e.em1 : 1.0 - scale2k(1.0 + e.em1, e.k);
 }
 
+// e^{-z} and 1 - e^{-z} from one exponential: bitwise exp_f64(-z) and
+// one_minus_exp_neg(z).
+struct ExpNeg {
+  double q, om;
+};
+
+__device__ __forceinline__ ExpNeg exp_neg_pair(double z) {
+  const ExpParts e = exp_parts(-z);
+  const double q = scale2k(1.0 + e.em1, e.k);
+  return {q, (e.k == 0) ? -e.em1 : 1.0 - q};
+}
+
 // 1/y: hardware estimate refined by two Newton steps.
 __device__ __forceinline__ double rcp_f64(double y) {
   double r = __builtin_amdgcn_rcp(y);
@@ -274,7 +286,7 @@ struct Bracket {
   float t1;    // upper end (at/right of the crossing)
 };
 
-constexpr int kPeakIters = 5;   // Newton steps for t_p
+constexpr int kPeakIters = 4;   // Newton steps for t_p (g(t_p) within ~1e-4 nats of max g)
 constexpr int kUpperIters = 2;  // fixed-point steps before the final Newton step for t1
 constexpr int kLowerIters = 3;  // fixed-point steps for t0
 
@@ -358,16 +370,33 @@ __device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G,
 // output dtype.  The search margin adds one nat plus a term proportional to
 // the magnitudes that FP32 rounds, so the FP32 search cannot land inside the
 // exact log-eps set.
+// G64: the shift G = g(t_p) in FP64 (with Gx = g(t_p) + x without
+// cancellation, for the FP64 bins).  Otherwise (FP32 outputs) G is
+// log cosh(v t_p) - x (cosh t_p - 1) in FP32 hardware arithmetic, with
+// cosh t - 1 = 2 sinh^2(t/2), minus x in FP64: any finite shift gives the same
+// log K (log K = G + log(h S0) with S0 taken relative to the same G), and this
+// one's rounding (~1e-7 of log cosh(v t_p) and of x cosh t_p ~ v near the
+// peak; x itself enters exactly) moves the exponents by far less than the
+// margin.  It costs ~20 slots against ~90 for the FP64 form.
+template <bool G64 = true>
 __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_eps_margin) {
   Bracket b;
   const float vf = (float)v, xf = (float)x;
   const float lx = hlog2(xf);
   float tp = 0.0f;
   if (v * v > x) tp = peak_f32(vf, xf, lx);
-  const double Gx = g_plus_x_f64(v, x, (double)tp);
-  const double G = Gx - x;
-  const float Gf = (float)G;
   const float xcp = hexp2(fmaf(kLog2eF, tp, lx)) + hexp2(fmaf(-kLog2eF, tp, lx));  // 2 x cosh t_p
+  double G, Gx;
+  if constexpr (G64) {
+    Gx = g_plus_x_f64(v, x, (double)tp);
+    G = Gx - x;
+  } else {
+    const float eh = hexp2(0.5f * kLog2eF * tp);
+    const float sh = 0.5f * (eh - hrcp(eh));  // sinh(t_p / 2)
+    Gx = (double)fmaf(-2.0f * xf, sh * sh, log_cosh_f32(vf * tp));
+    G = Gx - x;
+  }
+  const float Gf = (float)G;
   const float L = log_eps_margin + 1.0f + 1e-6f * (fabsf(Gf) + xcp);
   b.G = G;
   b.Gx = Gx;
@@ -468,8 +497,8 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const double xh = 0.5 * x;
   const Expm1Pair hh = expm1_pair(h);
   const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
-  const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
+  const ExpNeg qh = exp_neg_pair(2.0 * v * h);
+  const double Q = qh.q, E2 = qh.om;  // e^{-2vh}, 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
   double u = 2.0 - r;
   BinSums s{};
@@ -562,8 +591,8 @@ __device__ __forceinline__ BinSums bins_f32(int nb, double v, double x, double G
   const double E0i = rcp_f64(E0);
   double Cp = 0.5 * (E0 * ehi + E0i * eh);  // cosh(t0 - h)
   double C = 0.5 * (E0 + E0i);              // cosh(t0)
-  const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);  // 1 - Q
+  const ExpNeg qh = exp_neg_pair(2.0 * v * h);
+  const double Q = qh.q, E2 = qh.om;  // e^{-2vh}, 1 - Q
   double r = one_minus_exp_neg(2.0 * v * t0);
   double u = 2.0 - r;
   const double L0 = fma(vl, t0, -Gl);  // (v t - G - log 2) log2 e
@@ -670,8 +699,8 @@ __device__ __forceinline__ BinSums sub_bins_f32(int nb, int m_lo, int m_hi, bool
   const double Eai = rcp_f64(Ea);
   double Cp = 0.5 * (Ea * ehi + Eai * eh);
   double C = 0.5 * (Ea + Eai);
-  const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  const ExpNeg qh = exp_neg_pair(2.0 * v * h);
+  const double Q = qh.q, E2 = qh.om;
   double r = one_minus_exp_neg(2.0 * v * ta);
   double u = 2.0 - r;
   double L = fma((double)m_lo, dL, fma(vl, t0, -Gl));
@@ -715,8 +744,8 @@ __device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool
   const double xh = 0.5 * x;
   const Expm1Pair hh = expm1_pair(h);
   const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
-  const double Q = exp_f64(-2.0 * v * h);
-  const double E2 = one_minus_exp_neg(2.0 * v * h);
+  const ExpNeg qh = exp_neg_pair(2.0 * v * h);
+  const double Q = qh.q, E2 = qh.om;
   double r = one_minus_exp_neg(2.0 * v * fma((double)m_lo, h, t0));
   double u = 2.0 - r;
   Expm1Pair an{0.0, 0.0};

@@ -70,7 +70,7 @@ __global__ __launch_bounds__(kBlock) void k_gh_partial(int64_t nsamp, int64_t nc
         G = (double)lb.G, t0 = (double)lb.t0, t1 = (double)lb.t1;
       }
       if (!ok) {
-        const Bracket b = find_bracket(v, x, kMarginGh);
+        const Bracket b = find_bracket<false>(v, x, kMarginGh);
         s = bins_f32<true>(nb, v, x, b.G, (double)b.t0, (double)b.t1);
         G = b.G, t0 = (double)b.t0, t1 = (double)b.t1;
       }

@@ -92,7 +92,7 @@ __global__ __launch_bounds__(kBlock) void k_mlp_labels(int64_t n, const float* _
                                                        float* __restrict__ t1) {
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
-  const Bracket b = find_bracket(fabs((double)v[i]), (double)x[i], kMarginF32);
+  const Bracket b = find_bracket<false>(fabs((double)v[i]), (double)x[i], kMarginF32);
   t0[i] = b.t0;
   t1[i] = b.t1;
 }
@@ -763,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_logk_fallback(int nbins, const int* 
     const double vs = (double)vin[i];
     const double x = (double)xin[i];
     const double v = fabs(vs);
-    const Bracket b = find_bracket(v, x, kMarginF32);
+    const Bracket b = find_bracket<false>(v, x, kMarginF32);
     if (t0o) {
       t0o[i] = b.t0;
       t1o[i] = b.t1;
