@@ -85,8 +85,8 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the kernels
 # are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "f5d3b7c962abdca104cac79dfca3a69b40445244762f9a1a10b30e4e028f97ea",
-           # fused (65672 * 2 + 65623 KiB) + fallback (251 * 2 + 52 KiB) per 2^24 elements
+TRAFFIC = {"sources_sha256": "ce01d3da3eda21f54db99d242ee608d30413c02972237499f38c896e62ad9dff",
+           # fused (65672 * 2 + 65622 KiB) + fallback (251 * 2 + 52 KiB) per 2^24 elements
            "bytes_per_elem": 12.056}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp", "bessel_learned.hpp",
                    "bessel_kernels.hip", "bessel_gh.hip")

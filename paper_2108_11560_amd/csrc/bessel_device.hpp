@@ -97,13 +97,18 @@ __device__ __forceinline__ double exp_f64(double a) {
 // one ldexp apply the table entry and 2^k; the per-node cost is 12 VALU slots
 // against 15 for a degree-9 polynomial on |r| <= ln2/2, at the same accuracy.
 __shared__ double s_exp2_table[256];
+// 2^{j/256} - 1 to full relative accuracy (expm1_pair_tab).
+__shared__ double s_exp2m1_table[256];
 
 // Every thread of a block calls it before any thread of the block reaches
-// exp_node_f64, then the block synchronises.  Blocks have kBlock = 256 threads,
-// one entry each.
+// exp_node_f64 or expm1_pair_tab, then the block synchronises.  Blocks have
+// kBlock = 256 threads, one entry each.
 __device__ __forceinline__ void exp2_table_init() {
   const int j = threadIdx.x & 255;
-  s_exp2_table[j] = exp_f64((double)j * (kLn2D / 256.0));
+  const ExpParts e = exp_parts((double)j * (kLn2D / 256.0));  // k = 0 for j < 128, 1 above
+  const double T = scale2k(1.0 + e.em1, e.k);
+  s_exp2_table[j] = T;
+  s_exp2m1_table[j] = (e.k == 0) ? e.em1 : T - 1.0;  // T - 1 exact for T in [1, 2]
 }
 
 __device__ __forceinline__ double exp_node_f64(double a) {
@@ -204,6 +209,29 @@ struct Expm1Pair {
 __device__ __forceinline__ Expm1Pair expm1_pair(double t) {
   const ExpParts e = exp_parts(t);
   const double m = (e.k == 0) ? e.em1 : scale2k(1.0 + e.em1, e.k) - 1.0;  // e^t >= e^{ln2/2} when k > 0
+  return {m, m * rcp_f64(1.0 + m)};
+}
+
+// The same pair from the block's tables (exp2_table_init), for t >= 0: with
+// K = round(256 t log2 e) = 256 k + j and |r| <= ln2/512 as in exp_node_f64,
+// e^t = 2^k T_j e^r, and for k = 0 e^t - 1 = (T_j - 1) + T_j (e^r - 1) with
+// T_j - 1 from its own table, so no term cancels; e^r - 1 by its Taylor
+// polynomial of degree 5 (remainder below 1e-20 on |r| <= ln2/512).  For
+// k >= 1, e^t >= 2 and e^t - 1 has no cancellation.  About 25 slots against
+// 40 for expm1_pair.
+__device__ __forceinline__ Expm1Pair expm1_pair_tab(double t) {
+  const double kd = fma(t, 256.0 * kLog2e, kRoundMagic);
+  const double kf = kd - kRoundMagic;
+  const double r = fma(-kf, kLn2Lo / 256.0, fma(-kf, kLn2D / 256.0, t));
+  double p = fma(r, 1.0 / 120.0, 1.0 / 24.0);
+  p = fma(p, r, 1.0 / 6.0);
+  p = fma(p, r, 0.5);
+  p = fma(p, r, 1.0);
+  const double q = p * r;  // e^r - 1
+  const int K = __double2loint(kd);
+  const int j = K & 255, k = K >> 8;
+  const double e0 = fma(s_exp2_table[j], q, s_exp2m1_table[j]);  // T_j e^r - 1
+  const double m = (k == 0) ? e0 : scale2k(1.0 + e0, k) - 1.0;
   return {m, m * rcp_f64(1.0 + m)};
 }
 
@@ -417,7 +445,8 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
 // with A = v t - x cosh t - log 2, so each node needs one exponential of the
 // shifted argument A - G.  Along t_m = t0 + m h every other factor follows by
 // cheap recurrences instead of transcendentals:
-//   e^{t+h} = e^t e^h,  e^{-(t+h)} = e^{-t} e^{-h}       (FP64 path, re-anchored)
+//   e^{t+h} - 1 = (e^t - 1) e^h + (e^h - 1), and the same for 1 - e^{-t}
+//                                                        (FP64 path, re-anchored)
 //   cosh(t+h) = 2 cosh(h) cosh(t) - cosh(t-h)            (FP32 path)
 //   r(t+h) = r(t) e^{-2vh} + (1 - e^{-2vh})               (only positive terms,
 //                                                           so r = 1 - q stays
@@ -473,7 +502,8 @@ __device__ __forceinline__ void moments(double wu, double wr, double t, double d
 //   e^{t+h} - 1 = (e^t - 1) e^h + (e^h - 1),
 //   1 - e^{-(t+h)} = (1 - e^{-t}) e^{-h} + (1 - e^{-h}),
 // (relative error within ~m ulp after m steps, also as t -> 0), both
-// recomputed at each chunk start (every kChunk nodes).  f at a node is
+// recomputed at each chunk start (every kChunk nodes) from the block's tables
+// (expm1_pair_tab; the kernels build them with exp2_table_init).  f at a node is
 // e^{A} u with u = 2 - r = 1 + e^{-2vt} by its own recurrence (as in the FP32
 // bins); even and odd nodes are summed apart (independent FMA chains).
 // S_x = sum f cosh t is returned as S0 + sum f (cosh t - 1).
@@ -495,7 +525,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const double h = (t1 - t0) / (double)nb;
   const double Gs = Gx + kLn2;
   const double xh = 0.5 * x;
-  const Expm1Pair hh = expm1_pair(h);
+  const Expm1Pair hh = expm1_pair_tab(h);
   const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
   const ExpNeg qh = exp_neg_pair(2.0 * v * h);
   const double Q = qh.q, E2 = qh.om;  // e^{-2vh}, 1 - Q
@@ -507,7 +537,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   const int nchunks = nb / kChunk;
   for (int c = 0; c < nchunks; ++c) {
     const double ta = fma((double)(c * kChunk), h, t0);
-    Expm1Pair an = expm1_pair(ta);
+    Expm1Pair an = expm1_pair_tab(ta);
     double L = fma(v, ta, -Gs), t = ta, d = ta - ca;
 #pragma unroll
     for (int b = 0; b < kChunk; ++b) {
@@ -535,7 +565,7 @@ __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double G
   // remainder nodes (nb not a multiple of kChunk) and the last node m = nb
   for (int m = nchunks * kChunk; m <= nb; ++m) {
     const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-    const Expm1Pair an = expm1_pair(t);
+    const Expm1Pair an = expm1_pair_tab(t);
     const double P = an.ep * an.em;
     double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
     if (m == 0 || m == nb) w *= 0.5;
@@ -742,7 +772,7 @@ __device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool
   const double h = (t1 - t0) / (double)nb;
   const double Gs = Gx + kLn2;
   const double xh = 0.5 * x;
-  const Expm1Pair hh = expm1_pair(h);
+  const Expm1Pair hh = expm1_pair_tab(h);
   const double eh = 1.0 + hh.ep, ehi = 1.0 - hh.em;
   const ExpNeg qh = exp_neg_pair(2.0 * v * h);
   const double Q = qh.q, E2 = qh.om;
@@ -755,7 +785,7 @@ __device__ __forceinline__ BinSums sub_bins_f64(int nb, int m_lo, int m_hi, bool
   for (int m = m_lo; m <= m_hi; ++m) {
     if (m == m_hi && !with_end) break;
     const double t = (m == nb) ? t1 : fma((double)m, h, t0);
-    if ((m - m_lo) % kChunk == 0 || m == nb) an = expm1_pair(t);  // recurrences re-anchored every kChunk nodes
+    if ((m - m_lo) % kChunk == 0 || m == nb) an = expm1_pair_tab(t);  // recurrences re-anchored every kChunk nodes
     const double P = an.ep * an.em;  // 2 (cosh t - 1)
     double w = exp_node_f64(fma(-xh, P, fma(v, t, -Gs)));
     if (m == 0 || m == nb) w *= 0.5;
