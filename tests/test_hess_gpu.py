@@ -200,3 +200,19 @@ def test_validated_domain(bk, dt):
     v, x = workloads.domain_pairs(800, seed=61)
     err = check_against_oracle(bk, v, x, dt)
     print(dt, "max mixed error per output", err.max(axis=0))
+
+
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+@pytest.mark.parametrize("split", [False, True])
+def test_large_x_corners(bk, dt, split):
+    # the validated domain's large-x edge (x up to 1e6), where the bracket is
+    # ~1e-2 wide and cosh t - 1 ~ 1e-5 across it: the FP64 moments of cosh t
+    # are taken about cosh t_p - 1, the FP32 shift subtracts x exactly
+    v = np.repeat([0.0, 0.5, 10.0, 100.0, 1e3], 3)
+    x = np.tile([1e5, 3e5, 1e6], 5)
+    prev = bk.set_split_threshold(1 << 20 if split else 0)
+    try:
+        err = check_against_oracle(bk, v, x, dt)
+    finally:
+        bk.set_split_threshold(prev)
+    print(dt, "split" if split else "one lane", "max mixed error per output", err.max(axis=0))
