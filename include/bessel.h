@@ -24,7 +24,7 @@
  *     follows the dtype: eps = 2^-23 (F32) or 2^-52 (F64).
  *   - Output arrays must not overlap input arrays (BESSEL_ERR_ALIAS).
  *   - Sizes: elements are indexed with 64 bits; one call takes up to
- *     256 (2^31 - 1) elements (the launch grid), the learned range modes up to
+ *     256 x (2^31 - 1) elements (the launch grid), the learned range modes up to
  *     2^31 - 2 (their worklist holds 32-bit indices).  Larger n returns
  *     BESSEL_ERR_ARG before any work is queued.
  *   - Return value: BESSEL_OK (0), or a negative status; the message of the
