@@ -75,6 +75,10 @@ W_MLP_PRE = W_NET + 255.0
 # The same network read from its bilinear table: features 8, cell index 12,
 # two 16-byte loads, 6 FMAs, in place of the network's VALU work.
 W_TAB = 30.0
+# Issue-slot equivalents per element of the network's MFMAs (896 busy cycles
+# per wavefront / 4 cycles per wave instruction), reported beside the VALU
+# fraction, not counted in W.
+MFMA_SLOT_EQUIV = 224.0
 W_TAB_PRE = W_TAB + 255.0
 
 # MI355X vector issue peak: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz lane-slots/s
@@ -491,6 +495,12 @@ def main():
         "frac": achieved / PEAK_SLOTS,
         "traffic": traffic,
         "alg_slots_per_elem": head["alg_slots_per_elem"],
+        # the network's 56 f16 MFMAs per wavefront keep the matrix core busy
+        # 896 cycles, which the SIMD does not overlap with VALU issue: 224
+        # issue-slot equivalents per element (SQ_VALU_MFMA_BUSY_CYCLES / 4)
+        "mfma_slot_equiv_per_elem": MFMA_SLOT_EQUIV,
+        "frac_incl_mfma_issue": achieved * (head["alg_slots_per_elem"] + MFMA_SLOT_EQUIV)
+        / head["alg_slots_per_elem"] / PEAK_SLOTS,
     }
 
     line = {
