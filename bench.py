@@ -58,12 +58,12 @@ import workloads  # noqa: E402
 # (= 20.5), + 6 with d/dv and d/dx (t by addition, r, w r, w u, two sums),
 # + 13 more for the second derivatives (cosh t - 1 from the product, six
 # moments about the peak, two operations each).  W_PRE: peak (4 Newton steps)
-# 100, G (FP64 80, FP32 20), t1 50, t0 60, bin set-up 120, final log and
-# reciprocal 50, loads 20.  Keyed by (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2
+# 100, the shift G in FP32 arithmetic 20, t1 50, t0 60, bin set-up 120, final
+# log and reciprocal 50, loads 20.  Keyed by (dtype, derivative order): 0 log K, 1 with d/dv and d/dx, 2
 # with the second derivatives too.
 W_NODE = {("f32", 0): 9.0, ("f32", 1): 15.0, ("f32", 2): 21.0,
           ("f64", 0): 20.5, ("f64", 1): 26.5, ("f64", 2): 39.5}
-W_PRE = {"f32": 420.0, "f64": 480.0}
+W_PRE = 420.0
 # Learned bracket: the network's VALU work (64 first-layer clamps, two per
 # f16 conversion with its clamp bit, 32; 64 second-layer cubics, two per
 # packed group of 4 instructions -- conversion with clamp, one FMA, two
@@ -89,8 +89,8 @@ PEAK_SLOTS = 256 * 4 * 16 * 2.4e9
 # from rocprofv3 FETCH_SIZE (x2: a plain 256 MiB device copy reads back half
 # its size on this counter) plus WRITE_SIZE, taken on the sources the kernels
 # are compiled from (hashed below); reported only while they still match.
-TRAFFIC = {"sources_sha256": "ce01d3da3eda21f54db99d242ee608d30413c02972237499f38c896e62ad9dff",
-           # fused (65672 * 2 + 65622 KiB) + fallback (251 * 2 + 52 KiB) per 2^24 elements
+TRAFFIC = {"sources_sha256": "94a079235301eadf08b69f90148788bfdd596e4da198ccf01c1760e766b3fc44",
+           # fused (65672 * 2 + 65623 KiB) + fallback (251 * 2 + 52 KiB) per 2^24 elements
            "bytes_per_elem": 12.056}
 TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp", "bessel_learned.hpp",
                    "bessel_kernels.hip", "bessel_gh.hip")
@@ -98,8 +98,8 @@ TRAFFIC_SOURCES = ("bessel_mlp.hip", "bessel_device.hpp", "bessel_internal.hpp",
 # the SQ_INSTS_VALU_TRANS_F32 counter per wavefront of 64 elements on the same
 # sources (the FP64 paths' come from the FP32 bracket search; their
 # exponentials and logarithms are FP64 software)
-TRANS_F32_PER_ELEM = {"f32_fwd": 191, "f32_fwd_bwd": 192, "f32_hess": 192, "f64_fwd": 59, "f64_fwd_bwd": 59,
-                      "f64_hess": 59, "f32_mlp_fwd": 144, "f32_mlp_fwd_bwd": 145, "f32_mlp_table_fwd": 144,
+TRANS_F32_PER_ELEM = {"f32_fwd": 191, "f32_fwd_bwd": 192, "f32_hess": 192, "f64_fwd": 61, "f64_fwd_bwd": 61,
+                      "f64_hess": 61, "f32_mlp_fwd": 144, "f32_mlp_fwd_bwd": 145, "f32_mlp_table_fwd": 144,
                       "f32_mlp_table_fwd_bwd": 145, "gh_f32_fwd_bwd": 166}
 
 
@@ -114,7 +114,7 @@ def kernel_sources_sha256() -> str:
 
 
 def alg_slots(dt: str, der: int, nbins: int) -> float:
-    return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE[dt]
+    return (nbins + 1) * W_NODE[(dt, int(der))] + W_PRE
 
 
 def alg_slots_mlp(grad: bool, nbins: int, fallback_rate: float, pre: float = W_MLP_PRE) -> float:

@@ -307,8 +307,8 @@ __device__ __forceinline__ double rcp_of(double y) {
 // never waits on a slow lane.  All loops below have compile-time trip counts.
 // ---------------------------------------------------------------------------
 struct Bracket {
-  double G;    // g(t_p), FP64
-  double Gx;   // g(t_p) + x, FP64 without cancellation (the FP64 bins' shift)
+  double G;    // the shift: g(t_p) (see find_bracket for its arithmetic)
+  double Gx;   // G + x, formed without cancellation (the FP64 bins' shift)
   float tp;    // peak location (at or to the right of the true peak)
   float t0;    // lower end (0, or at/left of the crossing)
   float t1;    // upper end (at/right of the crossing)
@@ -398,14 +398,14 @@ __device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G,
 // output dtype.  The search margin adds one nat plus a term proportional to
 // the magnitudes that FP32 rounds, so the FP32 search cannot land inside the
 // exact log-eps set.
-// G64: the shift G = g(t_p) in FP64 (with Gx = g(t_p) + x without
-// cancellation, for the FP64 bins).  Otherwise (FP32 outputs) G is
-// log cosh(v t_p) - x (cosh t_p - 1) in FP32 hardware arithmetic, with
-// cosh t - 1 = 2 sinh^2(t/2), minus x in FP64: any finite shift gives the same
-// log K (log K = G + log(h S0) with S0 taken relative to the same G), and this
-// one's rounding (~1e-7 of log cosh(v t_p) and of x cosh t_p ~ v near the
-// peak; x itself enters exactly) moves the exponents by far less than the
-// margin.  It costs ~20 slots against ~90 for the FP64 form.
+// The shift G = g(t_p) and Gx = G + x.  Any finite shift gives the same
+// log K (log K = G + log(h S0) with S0 taken relative to the same G), so the
+// kernels take Gx = log cosh(v t_p) - x (cosh t_p - 1) in FP32 hardware
+// arithmetic (cosh t - 1 = 2 sinh^2(t/2)) and G = Gx - x in FP64: its rounding
+// (~1e-7 of log cosh(v t_p) and of x cosh t_p ~ v near the peak; x itself
+// enters exactly) moves the exponents by far less than the margin, for ~20
+// slots against ~90 for the FP64 form.  G64 (bessel_range's FP64 output,
+// which reports g(t_p) itself) forms both in FP64.
 template <bool G64 = true>
 __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_eps_margin) {
   Bracket b;

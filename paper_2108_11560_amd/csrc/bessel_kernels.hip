@@ -56,7 +56,7 @@ __global__ __launch_bounds__(kBlock) void k_logk(int64_t n, int nbins, const T* 
   double lk, dvv, dxv;
   if (!domain_special(vs, x, lk, dvv, dxv)) {
     const double v = fabs(vs);
-    const Bracket b = find_bracket<sizeof(T) == 8>(v, x, margin_of<T>());
+    const Bracket b = find_bracket<false>(v, x, margin_of<T>());
     const BinSums s = run_bins<T, GRAD ? 1 : 0>(nb, v, x, b);
     const double h = ((double)b.t1 - (double)b.t0) / (double)nb;
     constexpr bool F64 = sizeof(T) == 8;
@@ -144,7 +144,7 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess(int64_t n, int nbins, cons
   double lvv = __builtin_nan(""), lxx = __builtin_nan(""), lvx = __builtin_nan("");
   if (!domain_special(vs, x, lk, lv, lx)) {
     const double v = fabs(vs);
-    const Bracket b = find_bracket<sizeof(T) == 8>(v, x, margin_of<T>());
+    const Bracket b = find_bracket<false>(v, x, margin_of<T>());
     constexpr bool F64 = sizeof(T) == 8;
     BinSums s;
     if constexpr (F64) {
@@ -200,7 +200,7 @@ __global__ __launch_bounds__(kBlock) void k_logk_split(int64_t n, int nbins, con
   BinSums s{};
   Bracket b{};
   if (!special) {
-    b = find_bracket<sizeof(T) == 8>(v, x, margin_of<T>());
+    b = find_bracket<false>(v, x, margin_of<T>());
     const int m_lo = (k * nb) / kSplit, m_hi = ((k + 1) * nb) / kSplit;
     if constexpr (sizeof(T) == 8)
       s = sub_bins_f64<GRAD ? 1 : 0>(nb, m_lo, m_hi, k == kSplit - 1, v, x, b.Gx, (double)b.t0, (double)b.t1);
@@ -262,7 +262,7 @@ __global__ __launch_bounds__(kBlock) void k_logk_hess_split(int64_t n, int nbins
   BinSums s{};
   Bracket b{};
   if (!special) {
-    b = find_bracket<sizeof(T) == 8>(v, x, margin_of<T>());
+    b = find_bracket<false>(v, x, margin_of<T>());
     const int m_lo = (k * nb) / kSplit, m_hi = ((k + 1) * nb) / kSplit;
     if constexpr (F64) {
       const double ca = (double)b.tp;

@@ -24,8 +24,8 @@ def test_work_model():
     # W(n) = (n + 1) w_node + w_pre, per element, in lane-slots
     assert bench.alg_slots("f32", 0, 128) == 129 * 9 + 420
     assert bench.alg_slots("f32", 1, 128) == 129 * 15 + 420
-    assert bench.alg_slots("f64", 0, 128) == 129 * 20.5 + 480
-    assert bench.alg_slots("f64", 2, 64) == 65 * 39.5 + 480
+    assert bench.alg_slots("f64", 0, 128) == 129 * 20.5 + 420
+    assert bench.alg_slots("f64", 2, 64) == 65 * 39.5 + 420
     # learned range: the network replaces the searches; fallbacks add the Newton path
     assert bench.alg_slots_mlp(False, 128, 0.0) == 129 * 9 + 170 + 255
     assert bench.alg_slots_mlp(False, 128, 0.5) == 129 * 9 + 425 + 0.5 * (129 * 9 + 420)
