@@ -14,11 +14,14 @@
 //   - bracket search (t_p, t0, t1): FP32 hardware transcendentals, with one
 //     extra nat of margin that absorbs their rounding; every returned end is on
 //     the outside of its crossing, so the bracket is a superset;
-//   - the peak value G = g(t_p): FP64 (it is added straight to log K);
-//   - per-bin argument g(t_m) - G: FP64 linear recurrences for e^{t_m},
-//     e^{-t_m} and 1 - e^{-2 v t_m}, so no transcendental is spent on them;
+//   - the shift G ~ g(t_p): any finite value gives the same log K (it is
+//     subtracted in every node's exponent and added back to log K), so it is
+//     formed in FP32 arithmetic, with x subtracted exactly in FP64;
+//   - per-bin argument g(t_m) - G: FP64, from linear recurrences (e^{t_m} - 1
+//     and 1 - e^{-t_m}, or cosh t_m, and 1 - e^{-2 v t_m}), so no
+//     transcendental is spent on them;
 //   - per-bin exponential and sums: FP32 hardware exp2 (F32 path) or a
-//     Cody-Waite + Taylor FP64 exp (F64 path).
+//     table-driven FP64 exp (F64 path), summed in FP64.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -517,7 +520,7 @@ __device__ __forceinline__ void moments(double wu, double wr, double t, double d
 // DER: 0 = S0 only, 1 = also S_v, S_x, 2 = also the second-derivative sums,
 // taken about the centres ca (for t) and 1 + cb1 (for cosh t): the caller
 // passes the peak and its cosh - 1, within a few widths of the integrand's
-// means.  Gx = g(t_p) + x without cancellation (Bracket::Gx).
+// means.  Gx ~ g(t_p) + x, formed without cancellation (Bracket::Gx).
 template <int DER>
 __device__ __forceinline__ BinSums bins_f64(int nb, double v, double x, double Gx, double t0, double t1,
                                             double ca = 0.0, double cb1 = 0.0) {
