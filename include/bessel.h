@@ -35,15 +35,20 @@
  *     x == +inf -> log K = -inf;  |v| == inf with finite x > 0 -> log K = +inf;
  *     derivatives are NaN in all of these.  v < 0 is evaluated at |v|
  *     (K_{-v} = K_v) with d/dv negated; v == 0 gives d/dv == 0 exactly.
- *     0 < x < 1e-36, finite x > 1e36 and finite |v| > 1e18 -> NaN as well:
- *     beyond the range of the bracket search (which runs in FP32).
+ *     0 < x < 1e-36, finite x > 1e36, finite |v| > 1e6 and finite
+ *     |v| > 1.2e38 x -> NaN as well: beyond the range of the bracket search
+ *     (which runs in FP32 with fixed step counts).
  *   - Validated domain (tests against the CPU oracle at the default 128 bins):
  *     |v| <= 1e3 with 1e-6 <= x <= 1e6 at the F64 bar (mixed error 1e-12) and
  *     1e-35 <= x <= 1e6 at the F32 bar (1e-5).  Outside it the results stay
  *     finite but lose accuracy: below x ~ 1e-6 the bracket is so wide that 128
  *     bins resolve the d/dx integrand only to ~1e-10 (more bins restore it);
  *     far above x ~ 1e6 the FP32 bracket search widens the bracket by the
- *     FP32 rounding of g(t_p) ~ -x until 128 bins no longer resolve it.
+ *     FP32 rounding of g(t_p) ~ -x until 128 bins no longer resolve it; above
+ *     |v| ~ 2e4 the end searches stop short of the ends (their steps shrink as
+ *     1/v), which widens the bracket likewise: measured mixed errors of log K
+ *     grow to ~3e-7 at |v| = 1e5 and ~1e-5 near 1e6 (derivatives ~5e-4 and
+ *     ~3e-3), worst where x is near |v|.
  */
 #ifndef BESSEL_H
 #define BESSEL_H

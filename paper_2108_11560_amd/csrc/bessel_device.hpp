@@ -260,17 +260,24 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
 // represents; then logk, dv, dx hold the convention's values.
 // Smallest x: the upper end solves x cosh t = L with L up to ~37 (FP64
 // margin), so L / x must stay below the FP32 maximum.  Largest x: x itself
-// and g(t_p) ~ -x must stay well inside the FP32 range.  Largest |v|: the peak
-// search forms v^2 in FP32.  Finite inputs beyond these give NaN (documented
-// in the header), as do NaN inputs and x < 0.
+// and g(t_p) ~ -x must stay well inside the FP32 range.  Largest |v|: the
+// fixed-count end searches advance from the peak by ~L / v per step while the
+// bracket's half-width is ~sqrt(2 L / v), so for large v they stop far short
+// of the ends; beyond |v| ~ 1e7 the FP32 search leaves brackets that 128 bins
+// cannot resolve (non-finite sums).  Largest v / x: the upper end's
+// acosh((...) / x) forms ~2 v / x in FP32, which overflows near 1.7e38.
+// Finite inputs beyond these give NaN (documented in the header), as do NaN
+// inputs and x < 0.
 constexpr double kMinX = 1e-36;
 constexpr double kMaxX = 1e36;
-constexpr double kMaxV = 1e18;
+constexpr double kMaxV = 1e6;
+constexpr double kMaxVoverX = 1.2e38;
 
 __device__ __forceinline__ bool domain_special(double v, double x, double& logk, double& dv, double& dx) {
   const double nan_ = __builtin_nan("");
+  const bool finite_v = !__builtin_isinf(v);
   const bool beyond = (x > 0.0 && x < kMinX) || (x > kMaxX && !__builtin_isinf(x)) ||
-                      (fabs(v) > kMaxV && !__builtin_isinf(v));
+                      (finite_v && (fabs(v) > kMaxV || (x > 0.0 && fabs(v) > kMaxVoverX * x)));
   if (__builtin_isnan(v) || __builtin_isnan(x) || x < 0.0 || beyond) {
     logk = nan_; dv = nan_; dx = nan_;
     return true;

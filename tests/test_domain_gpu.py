@@ -5,8 +5,11 @@ make_domain_points.py, which calls only the oracle).
 Validated (the bars of the path, mixed error, 128 bins): |v| <= 1e3 and
 1e-6 <= x <= 1e6 in FP64 (1e-12), 1e-35 <= x <= 1e6 in FP32 (1e-5).  Beyond
 (1e-35 <= x < 1e-6 in FP64) the results are finite and within the looser
-bounds measured for them (FP64: 1e-8 on log K, 1e-4 on the derivatives); x
-below 1e-36 or above 1e36, and |v| above 1e18, give NaN by convention.
+bounds measured for them (FP64: 1e-8 on log K, 1e-4 on the derivatives).
+Orders 1e4, 1e5 and 1e6 (tests/golden/large_order_points.json, same script)
+are finite and within the bounds measured for them, which grow with v.  x
+below 1e-36 or above 1e36, |v| above 1e6 and |v| above 1.2e38 x give NaN by
+convention.
 """
 
 import json
@@ -20,6 +23,7 @@ pytestmark = pytest.mark.gpu
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 PTS = json.load(open(os.path.join(HERE, "golden", "domain_points.json")))["points"]
+LARGE = json.load(open(os.path.join(HERE, "golden", "large_order_points.json")))["points"]
 
 
 @pytest.fixture(scope="module")
@@ -31,10 +35,10 @@ def bk():
     return mod
 
 
-def run(bk, dt, split):
-    v = np.array([p["v"] for p in PTS])
-    x = np.array([p["x"] for p in PTS])
-    ref = np.array([[p["logk"], p["dv"], p["dx"]] for p in PTS])
+def run(bk, dt, split, pts=PTS):
+    v = np.array([p["v"] for p in pts])
+    x = np.array([p["x"] for p in pts])
+    ref = np.array([[p["logk"], p["dv"], p["dx"]] for p in pts])
     prev = bk.set_split_threshold(1 << 20 if split else 0)
     try:
         vt = torch.tensor(v, dtype=dt, device="cuda")
@@ -79,11 +83,31 @@ def test_below_range_is_nan(bk, dt):
 
 @pytest.mark.parametrize("dt", [torch.float64, torch.float32])
 def test_beyond_search_range_is_nan(bk, dt):
-    # x above 1e36 and finite |v| above 1e18: NaN by convention (x = +inf and
-    # |v| = +inf keep their limits); just inside, finite
-    v = torch.tensor([1.0, 1.0, 2e18, -2e18, 1.0, float("inf"), 1.0], dtype=dt, device="cuda")
-    x = torch.tensor([2e36, 1e38, 1.0, 1.0, float("inf"), 3.0, 5e35], dtype=dt, device="cuda")
-    lk, dv, dx = (t.double().cpu().numpy() for t in bk.logk_dv_dx(v, x))
-    assert np.isnan(lk[:4]).all() and np.isnan(dv[:4]).all() and np.isnan(dx[:4]).all()
-    assert lk[4] == -np.inf and lk[5] == np.inf
-    assert np.isfinite(lk[6])
+    # x above 1e36, finite |v| above 1e6 and |v| above 1.2e38 x: NaN by
+    # convention (x = +inf and |v| = +inf keep their limits); just inside,
+    # finite (v / x = 1e38 at v = 1e3, x = 1e-35 is in the validated domain)
+    v = torch.tensor([1.0, 1.0, 2e6, -2e6, 1e3, 1.0, float("inf"), 1.0, 9e5, -9e5, 1e3], dtype=torch.float64)
+    x = torch.tensor([2e36, 1e38, 1.0, 1.0, 5e-36, float("inf"), 3.0, 5e35, 1.0, 1e-30, 1e-35], dtype=torch.float64)
+    lk, dv, dx = (t.double().cpu().numpy() for t in bk.logk_dv_dx(v.to(dt).cuda(), x.to(dt).cuda()))
+    assert np.isnan(lk[:5]).all() and np.isnan(dv[:5]).all() and np.isnan(dx[:5]).all()
+    assert lk[5] == -np.inf and lk[6] == np.inf
+    assert np.isfinite(lk[7:]).all() and np.isfinite(dv[7:]).all() and np.isfinite(dx[7:]).all()
+
+
+# mixed-error bounds at orders beyond the validated domain (log K, derivatives):
+# the validated bars at 1e4, and about ten times the largest errors measured at
+# these points at 1e5 (2.6e-7, 5.4e-4) and 1e6 (4.1e-6, 3.1e-3), both dtypes
+LARGE_BOUNDS = {
+    torch.float64: {1e4: (1e-12, 1e-12), 1e5: (2e-6, 5e-3), 1e6: (4e-5, 3e-2)},
+    torch.float32: {1e4: (1e-5, 1e-5), 1e5: (2e-6, 5e-3), 1e6: (4e-5, 3e-2)},
+}
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_large_orders(bk, dt, split):
+    v, x, got, err = run(bk, dt, split, LARGE)
+    assert np.isfinite(got).all()
+    for i in range(v.size):
+        b0, b1 = LARGE_BOUNDS[dt][v[i]]
+        assert err[i, 0] <= b0 and err[i, 1:].max() <= b1, (v[i], x[i], err[i])

@@ -6,7 +6,8 @@ sum.  A dropped term, a wrong sign or a wrong index in the integrands, the peak,
 the truncation interval or the derivative integrals fails at least one of them:
 
 * the integrand of Eq. (1)-(2)      -> closed forms at v = 1/2, 3/2; mpmath; scipy K0/K1;
-                                      order recurrence; Hankel bound; small-x limits
+                                      order recurrence; Hankel bound; small-x limits;
+                                      the uniform large-order expansion (v to 1e5)
 * d/dx (Section 4.1, Eq. (13))      -> recurrence identity for K'_v; closed forms at 1/2, 3/2
 * d/dv (Section 4.1, Eq. (13))      -> DLMF 10.38.7 at v = 1/2; v = 0; oddness; mpmath diff;
                                       Richardson differences of log K
@@ -170,6 +171,38 @@ def test_hankel_expansion_with_bound():
             ref = mp.log(mp.sqrt(mp.pi / (2 * x))) - x + mp.log(s)
             got = oracle.logk(v, x)[0]
             assert abs(got - float(ref)) <= float(bound) * 1.01 + 3e-16 * max(1.0, abs(float(ref)))
+
+
+def debye_logk(v, x):
+    """log K_v(x) by the uniform large-order expansion (DLMF 10.41.4, with the
+    polynomials u_1..u_3 of DLMF 10.41.10-11), and the size of its last term."""
+    v, x = mp.mpf(v), mp.mpf(x)
+    z = x / v
+    s = mp.sqrt(1 + z * z)
+    p = 1 / s
+    eta = s + mp.log(z / (1 + s))
+    u1 = (3 * p - 5 * p**3) / 24
+    u2 = (81 * p**2 - 462 * p**4 + 385 * p**6) / 1152
+    u3 = (30375 * p**3 - 369603 * p**5 + 765765 * p**7 - 425425 * p**9) / 414720
+    series = 1 - u1 / v + u2 / v**2 - u3 / v**3
+    return mp.log(mp.pi / (2 * v)) / 2 - v * eta - mp.log(1 + z * z) / 4 + mp.log(series), abs(u3 / v**3)
+
+
+def test_large_order_debye():
+    # Orders far above the other pins: the truncation interval is then ~1/sqrt(v)
+    # wide around a peak at t ~ asinh(v/x).  The expansion's error after u_3 is of
+    # the order of u_4 / v^4 (< 1e-15 here); twice the last kept term bounds it.
+    mp.mp.dps = 40
+    xs = np.array([1e-30, 1e-3, 1.0, 1e2, 1e3, 1e4, 1e5, 1e6])
+    for v in [2e3, 1e4, 1e5]:
+        lk, dv, dx = oracle.logk(np.full(xs.size, v), xs, deriv=True)
+        for i, x in enumerate(xs):
+            ref, last = debye_logk(v, x)
+            ref_v = mp.diff(lambda q: debye_logk(q, x)[0], v)
+            ref_x = mp.diff(lambda q: debye_logk(v, q)[0], x)
+            assert abs(lk[i] - float(ref)) <= 2e-15 * max(1.0, abs(float(ref))) + 2 * float(last), (v, x)
+            assert mixed_err(dv[i], float(ref_v)) <= 1e-14, (v, x)
+            assert mixed_err(dx[i], float(ref_x)) <= 1e-14, (v, x)
 
 
 def test_small_argument_limits():
