@@ -317,9 +317,11 @@ int bessel_mlp_fallback_count(const bessel_mlp* mlp, int* count);
  * This is the Bessel factor of a generalised-hyperbolic log-likelihood (the
  * application named in the paper's introduction), evaluated with the FP32
  * path and its derivatives (Sections 2 and 4.1) and the chain rule.  Sums are
- * accumulated in FP64 and reduced in a fixed order (deterministic).  The call
- * allocates a temporary of nsets * ceil(nsamp/256) * 5 doubles, stream-ordered
- * on hip_stream.  range_mode: BESSEL_RANGE_NEWTON (mlp ignored) or
+ * accumulated in FP64 and reduced in a fixed order (deterministic).  Each
+ * term follows bessel_logk's per-element conventions (a NaN or infinite term,
+ * e.g. |lam - 1/2| above 1e6, makes its set's sum and gradients non-finite).
+ * The call allocates a temporary of nsets * ceil(nsamp/256) * 5 doubles,
+ * stream-ordered on hip_stream.  range_mode: BESSEL_RANGE_NEWTON (mlp ignored) or
  * BESSEL_RANGE_MLP_TABLE (mlp required: the bracket from the predictor's
  * table, checked after the bins as in bessel_logk; an element that fails the
  * check takes the Newton bracket in the same pass, so no worklist is kept and
