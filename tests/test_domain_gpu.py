@@ -111,3 +111,24 @@ def test_large_orders(bk, dt, split):
     for i in range(v.size):
         b0, b1 = LARGE_BOUNDS[dt][v[i]]
         assert err[i, 0] <= b0 and err[i, 1:].max() <= b1, (v[i], x[i], err[i])
+
+
+@pytest.mark.parametrize("split", [False, True])
+@pytest.mark.parametrize("dt", [torch.float64, torch.float32])
+def test_search_range_limits_on_every_path(bk, dt, split):
+    # the same limits on log K alone, the second derivatives and bessel_range
+    v = torch.tensor([2e6, 1e3, 9e5, 1e3], dtype=torch.float64).to(dt).cuda()
+    x = torch.tensor([1.0, 5e-36, 1.0, 1e-35], dtype=torch.float64).to(dt).cuda()
+    prev = bk.set_split_threshold(1 << 20 if split else 0)
+    try:
+        lk = bk.logk(v, x).double().cpu().numpy()
+        hs = [t.double().cpu().numpy() for t in bk.logk_hess(v, x)]
+        rg = [t.double().cpu().numpy() for t in bk.bessel_range(v, x)]
+    finally:
+        bk.set_split_threshold(prev)
+    for out in [lk, hs[0]] + rg:
+        assert np.isnan(out[:2]).all() and np.isfinite(out[2:]).all()
+    # inside, the derivatives are not NaN; in FP32 they may overflow where their
+    # value does (d2/dx2 ~ v / x^2 = 1e73 at v = 1e3, x = 1e-35)
+    for out in hs[1:]:
+        assert np.isnan(out[:2]).all() and not np.isnan(out[2:]).any()

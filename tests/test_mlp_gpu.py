@@ -264,12 +264,15 @@ def test_learned_range_domain_conventions(mods, trained, mode):
     bk, M = mods
     mlp, _ = trained
     nan, inf = float("nan"), float("inf")
-    v = dev32([nan, 1.0, 1.0, 1.0, 1.0, inf, 2.5, -2.5])
-    x = dev32([1.0, nan, -1.0, 0.0, inf, 2.0, 3.0, 3.0])
+    # the last four: beyond the bracket search's range (|v| > 1e6, v > 1.2e38 x)
+    # NaN, as on the Newton path; just inside, finite
+    v = dev32([nan, 1.0, 1.0, 1.0, 1.0, inf, 2.5, -2.5, 2e6, 1e3, 9e5, 1e3])
+    x = dev32([1.0, nan, -1.0, 0.0, inf, 2.0, 3.0, 3.0, 1.0, 5e-36, 1.0, 1e-35])
     lk = host(bk.logk(v, x, range=mode, mlp=mlp))
     assert np.isnan(lk[:3]).all()
     assert lk[3] == np.inf and lk[4] == -np.inf and lk[5] == np.inf
     assert lk[6] == lk[7]
+    assert np.isnan(lk[8:10]).all() and np.isfinite(lk[10:]).all()
 
 
 @pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
