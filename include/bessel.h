@@ -40,15 +40,18 @@
  *     (which runs in FP32 with fixed step counts).
  *   - Validated domain (tests against the CPU oracle at the default 128 bins):
  *     |v| <= 1e3 with 1e-6 <= x <= 1e6 at the F64 bar (mixed error 1e-12) and
- *     1e-35 <= x <= 1e6 at the F32 bar (1e-5).  Outside it the results stay
- *     finite but lose accuracy: below x ~ 1e-6 the bracket is so wide that 128
- *     bins resolve the d/dx integrand only to ~1e-10 (more bins restore it);
- *     far above x ~ 1e6 the FP32 bracket search widens the bracket by the
- *     FP32 rounding of g(t_p) ~ -x until 128 bins no longer resolve it; above
- *     |v| ~ 2e4 the end searches stop short of the ends (their steps shrink as
- *     1/v), which widens the bracket likewise: measured mixed errors of log K
- *     grow to ~3e-7 at |v| = 1e5 and ~1e-5 near 1e6 (derivatives ~5e-4 and
- *     ~3e-3), worst where x is near |v|.
+ *     1e-35 <= x <= 1e6 at the F32 bar (1e-5).  Larger orders, tested at
+ *     |v| = 1e4, 1e5 and 1e6 for x from 1e-30 to 1e6: log K and its first
+ *     derivatives hold the same bars (measured <= 4e-13 F64, <= 1e-7 F32);
+ *     the F64 second derivatives in x hold ~1e-11 at 1e5 and ~4e-10 at 1e6
+ *     (the variance of cosh t about cosh t_p over a bracket narrower than
+ *     1e-2 cancels a few digits).  Outside the validated x range the results
+ *     stay finite but lose accuracy: below x ~ 1e-6 the bracket is so wide
+ *     that 128 bins resolve the d/dx integrand only to ~1e-10 (more bins
+ *     restore it); far above x ~ 1e6 the FP32 bracket search widens the
+ *     bracket by the FP32 rounding of g(t_p) ~ -x until 128 bins no longer
+ *     resolve it.  F32 derivatives whose value exceeds the F32 range (e.g.
+ *     d2/dx2 ~ v / x^2 at small x) are +-inf.
  */
 #ifndef BESSEL_H
 #define BESSEL_H

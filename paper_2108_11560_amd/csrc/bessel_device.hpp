@@ -261,11 +261,11 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
 // Smallest x: the upper end solves x cosh t = L with L up to ~37 (FP64
 // margin), so L / x must stay below the FP32 maximum.  Largest x: x itself
 // and g(t_p) ~ -x must stay well inside the FP32 range.  Largest |v|: the
-// fixed-count end searches advance from the peak by ~L / v per step while the
-// bracket's half-width is ~sqrt(2 L / v), so for large v they stop far short
-// of the ends; beyond |v| ~ 1e7 the FP32 search leaves brackets that 128 bins
-// cannot resolve (non-finite sums).  Largest v / x: the upper end's
-// acosh((...) / x) forms ~2 v / x in FP32, which overflows near 1.7e38.
+// search's margin for its own FP32 rounding grows as 1e-6 |g(t_p)| ~ 1e-6 v t_p,
+// so the bracket's half-width stays near sqrt(2e-6 t_p) while the integrand's
+// width 1/sqrt(v) shrinks; from |v| ~ 1e7 on, 128 bins no longer resolve it.
+// Largest v / x: the upper end's acosh((...) / x) (the fixed-count search used
+// up to |v| = 1e3) forms ~2 v / x in FP32, which overflows near 1.7e38.
 // Finite inputs beyond these give NaN (documented in the header), as do NaN
 // inputs and x < 0.
 constexpr double kMinX = 1e-36;
@@ -404,6 +404,79 @@ __device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G,
   return fminf(t, tp);
 }
 
+// Large orders (|v| above the validated 1e3, peak t_p > 0).  The steps of
+// upper_f32 / lower_f32 move ~L / v per iteration while the bracket's
+// half-width is ~sqrt(2 L / v), so for large v a fixed count of them stops far
+// from the ends (the bracket stays valid but widens several-fold, and the bins
+// lose resolution).  Here each end starts from a bound instead.  The third
+// derivative of g is <= 0 on t >= 0 (that of log cosh(v t) and that of
+// -x cosh t both are), so g'' decreases:
+//   right of t_p (where g'(t_p) <= 0: the peak search ends at or right of the
+//   root) g lies below the parabola g(t_p) - a d^2 / 2, a = -g''(t_p), so
+//   t_p + sqrt(2 L / a) is outside;
+//   left of t_p, over [t_l, t_p] the curvature is at least a_l = -g''(t_l), so
+//   if w = sqrt(2 L / a_l) <= t_p - t_l, t_p - w is outside.
+// For large v these bounds are nearly tight (F ~ 0 there, within the FP32
+// rounding of F), so each start sits kLargeOut times further out (F ~ -0.56 L).
+// From an outside point Newton steps on the concave F = g - G + L stay outside
+// and converge (the tangent lies above F).  Where a start is not outside by
+// the FP32 evaluation of F, the fixed-count searches above are used instead.
+struct GDerivs {
+  float F, gp, a;  // F = g - G + L, g', -g''
+};
+__device__ __forceinline__ GDerivs g_derivs_f32(float v, float lx, float t, float G, float L) {
+  const float q = hexp2(-2.0f * kLog2eF * v * t);  // e^{-2 v t}
+  const float rq = hrcp(1.0f + q);
+  const float xe = hexp2(fmaf(kLog2eF, t, lx));    // x e^{t}
+  const float xei = hexp2(fmaf(-kLog2eF, t, lx));  // x e^{-t}
+  GDerivs d;
+  d.F = v * t + (hlog2(1.0f + q) - 1.0f) * kLn2F - 0.5f * (xe + xei) - G + L;
+  d.gp = v * (1.0f - q) * rq - 0.5f * (xe - xei);
+  d.a = 0.5f * (xe + xei) - v * v * (4.0f * q * rq * rq);
+  return d;
+}
+
+constexpr float kLargeV = 1e3f;  // above it the ends start from the bounds
+constexpr int kLargeNewton = 2;  // Newton steps from each outside start
+constexpr float kLargeOut = 1.25f;
+
+__device__ __forceinline__ float upper_large_f32(float v, float x, float lx, float tp, float G, float L) {
+  const GDerivs d0 = g_derivs_f32(v, lx, tp, G, L);
+  float t = tp + kLargeOut * hsqrt(2.0f * L * hrcp(d0.a));
+  GDerivs d = g_derivs_f32(v, lx, t, G, L);
+  if (!(d0.a > 0.0f && d.F < 0.0f && d.gp < 0.0f)) return upper_f32(v, x, lx, tp, G, L);
+#pragma unroll
+  for (int k = 0; k < kLargeNewton; ++k) {
+    const float tn = t - d.F * hrcp(d.gp);
+    const GDerivs dn = g_derivs_f32(v, lx, tn, G, L);
+    // keep only steps that stay outside (F < 0) and move inward
+    if (!(dn.F < 0.0f && dn.gp < 0.0f && tn < t)) break;
+    t = tn;
+    d = dn;
+  }
+  return t;
+}
+
+__device__ __forceinline__ float lower_large_f32(float v, float lx, float tp, float G, float L) {
+  const GDerivs dp = g_derivs_f32(v, lx, tp, G, L);
+  const float D = 2.0f * hsqrt(2.0f * L * hrcp(dp.a));
+  const float tl = fmaxf(tp - D, 0.0f);
+  const GDerivs dl = g_derivs_f32(v, lx, tl, G, L);
+  const float w = kLargeOut * hsqrt(2.0f * L * hrcp(dl.a));
+  float t = tp - w;
+  GDerivs d = g_derivs_f32(v, lx, t, G, L);
+  if (!(dp.a > 0.0f && dl.a > 0.0f && w <= tp - tl && d.F < 0.0f && d.gp > 0.0f)) return lower_f32(v, lx, tp, G, L);
+#pragma unroll
+  for (int k = 0; k < kLargeNewton; ++k) {
+    const float tn = t - d.F * hrcp(d.gp);
+    const GDerivs dn = g_derivs_f32(v, lx, tn, G, L);
+    if (!(dn.F < 0.0f && dn.gp > 0.0f && tn > t)) break;
+    t = tn;
+    d = dn;
+  }
+  return fminf(t, tp);
+}
+
 // Full bracket for v >= 0 and finite x > 0.  log_eps_margin = -log eps of the
 // output dtype.  The search margin adds one nat plus a term proportional to
 // the magnitudes that FP32 rounds, so the FP32 search cannot land inside the
@@ -439,9 +512,14 @@ __device__ __forceinline__ Bracket find_bracket(double v, double x, float log_ep
   b.G = G;
   b.Gx = Gx;
   b.tp = tp;
-  b.t1 = upper_f32(vf, xf, lx, tp, Gf, L);
   const bool need_t0 = (-x - G + (double)L) <= 0.0;
-  b.t0 = need_t0 ? lower_f32(vf, lx, tp, Gf, L) : 0.0f;
+  if (vf > kLargeV && tp > 0.0f) {
+    b.t1 = upper_large_f32(vf, xf, lx, tp, Gf, L);
+    b.t0 = need_t0 ? lower_large_f32(vf, lx, tp, Gf, L) : 0.0f;
+  } else {
+    b.t1 = upper_f32(vf, xf, lx, tp, Gf, L);
+    b.t0 = need_t0 ? lower_f32(vf, lx, tp, Gf, L) : 0.0f;
+  }
   return b;
 }
 

@@ -1,7 +1,7 @@
 """Write domain_points.json: the oracle's log K_v(x), d/dv and d/dx at the
 corners of the domain the GPU path is validated on (and a little beyond), and
-large_order_points.json: the same at orders v = 1e4, 1e5, 1e6, beyond that
-domain, where the GPU path's accuracy degrades with v.
+large_order_points.json: the same and the second derivatives at orders
+v = 1e4, 1e5, 1e6, beyond that domain.
 
     python tests/golden/make_domain_points.py
 
@@ -26,11 +26,15 @@ V_LARGE = [1e4, 1e5, 1e6]
 X_LARGE = [1e-30, 1e-3, 1.0, 1e3, 1e4, 1e5, 1e6]
 
 
-def write(name, vs, xs):
+def write(name, vs, xs, second=False):
     vv, xx = (a.ravel() for a in np.meshgrid(vs, xs, indexing="ij"))
     lk, dv, dx = oracle.logk(vv, xx, deriv=True)
     points = [{"v": float(a), "x": float(b), "logk": float(c), "dv": float(d), "dx": float(e)}
               for a, b, c, d, e in zip(vv, xx, lk, dv, dx)]
+    if second:
+        h = oracle.logk_hess(vv, xx)
+        for p, row in zip(points, h):
+            p["d2v"], p["d2x"], p["dvx"] = (float(q) for q in row[3:])
     out = {"source": "oracle/oracle.c oracle_logk_batch (this script)", "points": points}
     with open(os.path.join(HERE, name), "w") as f:
         json.dump(out, f, indent=1)
@@ -39,7 +43,7 @@ def write(name, vs, xs):
 
 def main():
     write("domain_points.json", V, X)
-    write("large_order_points.json", V_LARGE, X_LARGE)
+    write("large_order_points.json", V_LARGE, X_LARGE, second=True)
 
 
 if __name__ == "__main__":

@@ -205,6 +205,20 @@ def test_large_order_debye():
             assert mixed_err(dx[i], float(ref_x)) <= 1e-14, (v, x)
 
 
+def test_large_order_debye_second_derivatives():
+    # the oracle's second derivatives against those of the same expansion; the
+    # mixed one at x -> 0 (~ -1/x) is the least accurate, 2.9e-11 at v = 1e5
+    mp.mp.dps = 40
+    xs = np.array([1e-30, 1e-3, 1.0, 1e2, 1e3, 1e4, 1e5, 1e6])
+    f = lambda a, b: debye_logk(a, b)[0]  # noqa: E731
+    for v in [2e3, 1e4, 1e5]:
+        H = oracle.logk_hess(np.full(xs.size, v), xs)
+        for i, x in enumerate(xs):
+            refs = (mp.diff(f, (v, x), (2, 0)), mp.diff(f, (v, x), (0, 2)), mp.diff(f, (v, x), (1, 1)))
+            for k, r in enumerate(refs):
+                assert mixed_err(H[i, 3 + k], float(r)) <= 1e-10, (v, x, k)
+
+
 def test_small_argument_limits():
     # DLMF 10.30.2-3: K_v(x) ~ Gamma(v)/2 (2/x)^v (v > 0), K_0(x) ~ -log(x/2) - gamma.
     x = 1e-3
