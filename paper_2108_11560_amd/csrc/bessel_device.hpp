@@ -419,8 +419,11 @@ __device__ __forceinline__ float lower_f32(float v, float lx, float tp, float G,
 // For large v these bounds are nearly tight (F ~ 0 there, within the FP32
 // rounding of F), so each start sits kLargeOut times further out (F ~ -0.56 L).
 // From an outside point Newton steps on the concave F = g - G + L stay outside
-// and converge (the tangent lies above F).  Where a start is not outside by
-// the FP32 evaluation of F, the fixed-count searches above are used instead.
+// and converge (the tangent lies above F).  The fixed-count searches above run
+// as well, and each end takes the tighter of the two valid results: near a
+// flat peak (x ~ v^2, where -g''(t_p) is small) their bracket is the narrower
+// one, and they are the result where a start is not outside by the FP32
+// evaluation of F.
 struct GDerivs {
   float F, gp, a;  // F = g - G + L, g', -g''
 };
@@ -441,10 +444,11 @@ constexpr int kLargeNewton = 2;  // Newton steps from each outside start
 constexpr float kLargeOut = 1.25f;
 
 __device__ __forceinline__ float upper_large_f32(float v, float x, float lx, float tp, float G, float L) {
+  const float t_fixed = upper_f32(v, x, lx, tp, G, L);
   const GDerivs d0 = g_derivs_f32(v, lx, tp, G, L);
   float t = tp + kLargeOut * hsqrt(2.0f * L * hrcp(d0.a));
   GDerivs d = g_derivs_f32(v, lx, t, G, L);
-  if (!(d0.a > 0.0f && d.F < 0.0f && d.gp < 0.0f)) return upper_f32(v, x, lx, tp, G, L);
+  if (!(d0.a > 0.0f && d.F < 0.0f && d.gp < 0.0f)) return t_fixed;
 #pragma unroll
   for (int k = 0; k < kLargeNewton; ++k) {
     const float tn = t - d.F * hrcp(d.gp);
@@ -454,10 +458,11 @@ __device__ __forceinline__ float upper_large_f32(float v, float x, float lx, flo
     t = tn;
     d = dn;
   }
-  return t;
+  return fminf(t, t_fixed);
 }
 
 __device__ __forceinline__ float lower_large_f32(float v, float lx, float tp, float G, float L) {
+  const float t_fixed = lower_f32(v, lx, tp, G, L);
   const GDerivs dp = g_derivs_f32(v, lx, tp, G, L);
   const float D = 2.0f * hsqrt(2.0f * L * hrcp(dp.a));
   const float tl = fmaxf(tp - D, 0.0f);
@@ -465,7 +470,7 @@ __device__ __forceinline__ float lower_large_f32(float v, float lx, float tp, fl
   const float w = kLargeOut * hsqrt(2.0f * L * hrcp(dl.a));
   float t = tp - w;
   GDerivs d = g_derivs_f32(v, lx, t, G, L);
-  if (!(dp.a > 0.0f && dl.a > 0.0f && w <= tp - tl && d.F < 0.0f && d.gp > 0.0f)) return lower_f32(v, lx, tp, G, L);
+  if (!(dp.a > 0.0f && dl.a > 0.0f && w <= tp - tl && d.F < 0.0f && d.gp > 0.0f)) return t_fixed;
 #pragma unroll
   for (int k = 0; k < kLargeNewton; ++k) {
     const float tn = t - d.F * hrcp(d.gp);
@@ -474,7 +479,7 @@ __device__ __forceinline__ float lower_large_f32(float v, float lx, float tp, fl
     t = tn;
     d = dn;
   }
-  return fminf(t, tp);
+  return fminf(fmaxf(t, t_fixed), tp);
 }
 
 // Full bracket for v >= 0 and finite x > 0.  log_eps_margin = -log eps of the

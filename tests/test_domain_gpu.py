@@ -158,6 +158,10 @@ def test_large_order_brackets(bk, dt):
     rng = np.random.default_rng(41)
     v = 10.0 ** rng.uniform(3.0, 6.0, 4096)
     x = 10.0 ** rng.uniform(-30.0, 6.0, 4096)
+    # and flat peaks, x near v^2, where -g''(t_p) is small
+    vf = 10.0 ** rng.uniform(3.0, 3.5, 512)
+    v = np.concatenate([v, vf])
+    x = np.concatenate([x, vf * vf * (1.0 + 10.0 ** rng.uniform(-7.0, -1.0, 512) * rng.choice([-1.0, 1.0], 512))])
     if dt == torch.float32:
         v, x = v.astype(np.float32).astype(np.float64), x.astype(np.float32).astype(np.float64)
     t0, t1, tp, G = (t.double().cpu().numpy() for t in bk.bessel_range(torch.tensor(v, dtype=dt).cuda(),
