@@ -264,8 +264,9 @@ __device__ __forceinline__ float log_cosh_f32(float z) {
 // search's margin for its own FP32 rounding grows as 1e-6 |g(t_p)| ~ 1e-6 v t_p,
 // so the bracket's half-width stays near sqrt(2e-6 t_p) while the integrand's
 // width 1/sqrt(v) shrinks; from |v| ~ 1e7 on, 128 bins no longer resolve it.
-// Largest v / x: the upper end's acosh((...) / x) (the fixed-count search used
-// up to |v| = 1e3) forms ~2 v / x in FP32, which overflows near 1.7e38.
+// Largest v / x: the upper end's acosh((...) / x) in the fixed-count search
+// (which runs at every order) forms ~2 v / x in FP32, which overflows near
+// 1.7e38.
 // Finite inputs beyond these give NaN (documented in the header), as do NaN
 // inputs and x < 0.
 constexpr double kMinX = 1e-36;
