@@ -67,7 +67,8 @@ extern "C" {
 #define BESSEL_F64 1
 
 /* how [t0, t1] is found */
-#define BESSEL_RANGE_NEWTON 0 /* peak by Newton steps, ends by monotone fixed-point + Newton steps */
+#define BESSEL_RANGE_NEWTON 0 /* peak by Newton steps, ends by monotone fixed-point + Newton steps
+                                 (above |v| = 1e3 also from curvature bounds; the tighter end is kept) */
 #define BESSEL_RANGE_MLP 1    /* learned bracket with a per-element check and Newton fallback */
 #define BESSEL_RANGE_MLP_TABLE 2 /* the same network read from its bilinear table (see bessel_mlp) */
 
