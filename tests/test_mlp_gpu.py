@@ -542,3 +542,25 @@ def test_learned_range_outside_training_distribution(mods, trained, mode):
     _, rdv, rdx = bk.logk_dv_dx(vt.double(), xt.double())
     assert float(((dv.double() - rdv).abs() / rdv.abs().clamp_min(1.0)).max()) <= 1e-5
     assert float(((dx.double() - rdx).abs() / rdx.abs().clamp_min(1.0)).max()) <= 1e-5
+
+
+@pytest.mark.parametrize("mode", ["mlp", "mlp_table"])
+def test_learned_range_large_orders(mods, trained, mode):
+    # orders 1e4 to 1e6, far outside the training set: the check rejects the
+    # predictions and the Newton bracket (its large-order ends) takes over;
+    # log K and the first derivatives hold the FP32 bar against the oracle
+    import json
+    import os
+    bk, M = mods
+    mlp, _ = trained
+    pts = json.load(open(os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden",
+                                      "large_order_points.json")))["points"]
+    v = np.array([p["v"] for p in pts], dtype=np.float32)
+    x = np.array([p["x"] for p in pts], dtype=np.float32)
+    ref = np.array([[p["logk"], p["dv"], p["dx"]] for p in pts])
+    lk, dv, dx = (host(t).astype(np.float64) for t in bk.logk_dv_dx(dev32(v), dev32(x), range=mode, mlp=mlp))
+    got = np.stack([lk, dv, dx], axis=1)
+    assert np.isfinite(got).all()
+    err = np.abs(got - ref) / np.maximum(1.0, np.abs(ref))
+    assert err.max() <= 1e-5, err.max()
+    assert np.array_equal(host(bk.logk(dev32(v), dev32(x), range=mode, mlp=mlp)), lk.astype(np.float32))
